@@ -1,0 +1,981 @@
+// fpm_api.hip -- host runtime and C ABI of libfpm (declared in fpm.h).
+//
+// The runtime owns every device buffer: an index holds the length-sorted,
+// padded dictionary with its fingerprints and filter keys; a plan holds the
+// buffers of one match pipeline (query staging, work list, match keys and
+// output), so repeated runs reuse memory, and the batched schedule replays
+// one captured hipGraph.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fpm.h"
+#include "fpm_internal.hpp"
+
+using namespace fpm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fpm_status fail(fpm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+fpm_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? FPM_ENOMEM : FPM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess)                          \
+            return hip_fail(_e, #expr);                \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    return hipMalloc((void **)p, bytes);
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p)
+        (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+uint32_t bits_for(uint64_t n)  // bits to index 0..n-1 (at least 1)
+{
+    uint32_t b = 1;
+    while (b < 64 && (1ull << b) < n)
+        ++b;
+    return b;
+}
+
+int key_kind_for(int variant, uint32_t bits)
+{
+    if (variant == FPM_COUNT && bits == 32)
+        return kPop64;
+    if (variant == FPM_POS)
+        return bits == 16 ? kPos16 : kPos32;
+    return kPop32;
+}
+
+size_t key_bytes(int kind) { return kind == kPop64 ? 8 : 4; }
+
+fpm_status check_csr(const uint8_t *bytes, const uint64_t *offsets, uint32_t n, const char *what)
+{
+    if (!offsets || (n > 0 && !bytes && offsets[n] > offsets[0]))
+        return fail(FPM_EINVAL, "%s: null pointer", what);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (offsets[i + 1] < offsets[i])
+            return fail(FPM_EINVAL, "%s: offsets decrease at %u", what, i);
+        if (offsets[i + 1] - offsets[i] > (uint64_t)kMaxLen)
+            return fail(FPM_EINVAL, "%s: string %u is longer than %d", what, i, kMaxLen);
+    }
+    return FPM_OK;
+}
+
+// Device copy of a length-sorted, padded string set.
+struct StrSet {
+    uint32_t n = 0, cap_n = 0;
+    uint64_t cap_bytes = 0, str_cap = 0;
+    uint32_t *len = nullptr, *perm = nullptr, *soff = nullptr, *str = nullptr, *off = nullptr, *bdw = nullptr;
+    uint8_t *slen = nullptr;
+    void *key = nullptr;
+    uint32_t *fp_orig = nullptr;
+    uint32_t *inv = nullptr;
+
+    hipError_t alloc(uint32_t max_n, uint64_t max_bytes, int kind, bool want_fp_orig, bool want_inv)
+    {
+        cap_n = max_n;
+        cap_bytes = max_bytes;
+        hipError_t e;
+        if ((e = dalloc(&len, max_n)) || (e = dalloc(&perm, max_n)) || (e = dalloc(&soff, max_n)) ||
+            (e = dalloc(&slen, max_n)) || (e = dalloc(&off, 257)) || (e = dalloc(&bdw, 257)))
+            return e;
+        // padded strings: sum over strings of max(1, ceil(L/4)) dwords, which is
+        // at most bytes/4 + n and at most 64 per string
+        str_cap = std::min<uint64_t>(max_bytes / 4 + (uint64_t)max_n, (uint64_t)max_n * 64) + 16;
+        if ((e = dalloc(&str, str_cap)))
+            return e;
+        // keys carry one filter chunk of padding (read, never used)
+        if ((e = dalloc((uint8_t **)&key, ((size_t)max_n + 64) * key_bytes(kind))))
+            return e;
+        if ((e = hipMemset(key, 0, ((size_t)max_n + 64) * key_bytes(kind))))
+            return e;
+        if (want_fp_orig && (e = dalloc(&fp_orig, max_n)))
+            return e;
+        if (want_inv && (e = dalloc(&inv, max_n)))
+            return e;
+        return hipSuccess;
+    }
+    void release()
+    {
+        dfree(len);
+        dfree(perm);
+        dfree(soff);
+        dfree(str);
+        dfree(off);
+        dfree(bdw);
+        dfree(slen);
+        dfree(key);
+        dfree(fp_orig);
+        dfree(inv);
+    }
+    StrSetView view() const { return StrSetView{perm, slen, soff, str, off, key}; }
+};
+
+// Length sort, padded layout and fingerprints of n device strings.
+void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, uint32_t n, uint64_t nbytes_limit,
+                  const uint8_t *d_map, int variant, uint32_t bits, int kind, bool fingerprints, uint32_t *err,
+                  uint32_t *scratch, hipStream_t s)
+{
+    S.n = n;
+    launch_lengths(d_offsets, n, S.len, err, s);
+    launch_length_sort(S.len, n, S.perm, S.off, S.bdw, scratch, s);
+    launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str, S.str_cap,
+                  err, s);
+    if (fingerprints)
+        launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, S.fp_orig, S.key,
+                            kind, s);
+}
+
+struct DevCounters {
+    uint64_t n_out, survivors, cells, examined;
+    uint32_t err, n_pairs, n_items, counter;
+};
+
+}  // namespace
+
+struct fpm_index {
+    uint32_t n = 0;
+    int variant = 0;
+    uint32_t bits = 16;
+    int kind = kPop32;
+    uint8_t map[256];
+    uint8_t *d_map = nullptr;
+    StrSet words;
+    uint32_t h_off[257];
+    uint32_t wbits = 1;
+    int device = 0;
+};
+
+struct fpm_plan {
+    const fpm_index *ix = nullptr;
+    uint32_t max_q = 0;
+    uint64_t max_bytes = 0;
+    int metric = 0;
+    uint32_t k = 1;
+    fpm_options opt;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int kind = kPop32;
+    bool survivors_only = false;
+
+    StrSet q;
+    uint32_t *scratch = nullptr;
+    PairRec *pairs = nullptr;
+    DevCounters *ctr = nullptr;
+    uint64_t *keys = nullptr, *tmp = nullptr;
+    uint32_t *triples = nullptr;
+    uint64_t cap = 0;
+    int persistent_blocks = 0;
+
+    // last run
+    const uint8_t *last_bytes = nullptr;
+    const uint64_t *last_offsets = nullptr;
+    uint32_t last_nq = 0;
+    bool ran = false;
+    uint32_t host_items = 0;
+    uint64_t host_examined = 0;
+
+    hipGraphExec_t gexec = nullptr;
+    const uint8_t *g_bytes = nullptr;
+    const uint64_t *g_offsets = nullptr;
+    uint32_t g_nq = 0;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<PairRec> h_pairs;
+
+    fpm_status alloc_output(uint64_t cap_entries)
+    {
+        dfree(keys);
+        dfree(tmp);
+        dfree(triples);
+        cap = cap_entries;
+        HIPCHK(dalloc(&keys, cap));
+        HIPCHK(dalloc(&tmp, cap));
+        HIPCHK(dalloc(&triples, cap * 3));
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        return FPM_OK;
+    }
+};
+
+// ======================================================================
+extern "C" {
+
+const char *fpm_last_error(void) { return g_last_error.c_str(); }
+
+void fpm_free(void *p) { free(p); }
+
+int fpm_num_fields(fpm_variant variant, uint32_t bits)
+{
+    if (bits != 16 && bits != 32)
+        return -1;
+    switch (variant) {
+    case FPM_OCC:
+        return (int)bits;
+    case FPM_OCCH:
+    case FPM_COUNT:
+        return (int)bits / 2;
+    case FPM_POS:
+        return (int)(bits / 3 + bits % 3);
+    default:
+        return -1;
+    }
+}
+
+fpm_status fpm_select_symbols(const uint8_t *bytes, const uint64_t *offsets, uint32_t n, fpm_variant variant,
+                              uint32_t bits, fpm_symbols symbols, uint8_t map_out[256])
+{
+    g_last_error.clear();
+    const int nf = fpm_num_fields(variant, bits);
+    if (nf < 0)
+        return fail(FPM_EINVAL, "unknown variant %d or bits %u", (int)variant, bits);
+    if (symbols < FPM_COMMON || symbols > FPM_MIXED)
+        return fail(FPM_EINVAL, "symbol set must be common, rare or mixed");
+    if (!map_out)
+        return fail(FPM_EINVAL, "null map_out");
+    fpm_status st = check_csr(bytes, offsets, n, "dictionary");
+    if (st)
+        return st;
+    const uint64_t nbytes = offsets[n];
+    uint8_t *d_bytes = nullptr, *d_map = nullptr;
+    uint64_t *d_off = nullptr;
+    unsigned long long *d_hist = nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&]() {
+        dfree(d_bytes);
+        dfree(d_map);
+        dfree(d_off);
+        dfree(d_hist);
+        if (s)
+            (void)hipStreamDestroy(s);
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&d_bytes, nbytes + 4)) ||
+        (e = dalloc(&d_off, (size_t)n + 1)) || (e = dalloc(&d_map, 256)) || (e = dalloc(&d_hist, 256))) {
+        cleanup();
+        return hip_fail(e, "fpm_select_symbols alloc");
+    }
+    if (nbytes)
+        (void)hipMemcpyAsync(d_bytes, bytes, nbytes, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(d_off, offsets, sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s);
+    launch_zero(d_hist, 512, s);
+    launch_byte_histogram(d_bytes, d_off, n, d_hist, s);
+    launch_select_symbols(d_hist, nf, (int)symbols, d_map, s);
+    (void)hipMemcpyAsync(map_out, d_map, 256, hipMemcpyDeviceToHost, s);
+    e = hipStreamSynchronize(s);
+    cleanup();
+    if (e)
+        return hip_fail(e, "fpm_select_symbols");
+    return FPM_OK;
+}
+
+void fpm_index_destroy(fpm_index *ix)
+{
+    if (!ix)
+        return;
+    ix->words.release();
+    dfree(ix->d_map);
+    delete ix;
+}
+
+fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets, uint32_t n_words,
+                                  fpm_variant variant, uint32_t bits, fpm_symbols symbols, const uint8_t *custom_map,
+                                  fpm_index **out)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(FPM_EINVAL, "null out");
+    *out = nullptr;
+    const int nf = fpm_num_fields(variant, bits);
+    if (nf < 0)
+        return fail(FPM_EINVAL, "unknown variant %d or bits %u (16 or 32)", (int)variant, bits);
+    if (symbols < FPM_COMMON || symbols > FPM_CUSTOM)
+        return fail(FPM_EINVAL, "unknown symbol set %d", (int)symbols);
+    if (symbols == FPM_CUSTOM) {
+        if (!custom_map)
+            return fail(FPM_EINVAL, "custom symbol set needs a map");
+        for (int c = 0; c < 256; ++c)
+            if (custom_map[c] != 0xFF && custom_map[c] >= nf)
+                return fail(FPM_EINVAL, "custom map: byte %d -> field %d, variant has %d fields", c, custom_map[c], nf);
+    }
+    if (n_words == 0xFFFFFFFFu)
+        return fail(FPM_EINVAL, "too many words");
+    fpm_status st = check_csr(bytes, offsets, n_words, "dictionary");
+    if (st)
+        return st;
+    const uint64_t nbytes = offsets[n_words];
+
+    fpm_index *ix = new (std::nothrow) fpm_index();
+    if (!ix)
+        return fail(FPM_ENOMEM, "host allocation");
+    ix->n = n_words;
+    ix->variant = variant;
+    ix->bits = bits;
+    ix->kind = key_kind_for(variant, bits);
+    ix->wbits = bits_for(n_words);
+    (void)hipGetDevice(&ix->device);
+
+    uint8_t *d_bytes = nullptr;
+    uint64_t *d_off = nullptr;
+    unsigned long long *d_hist = nullptr;
+    uint32_t *scratch = nullptr, *d_err = nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&]() {
+        dfree(d_bytes);
+        dfree(d_off);
+        dfree(d_hist);
+        dfree(scratch);
+        dfree(d_err);
+        if (s)
+            (void)hipStreamDestroy(s);
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&d_bytes, nbytes + 4)) ||
+        (e = dalloc(&d_off, (size_t)n_words + 1)) || (e = dalloc(&d_hist, 256)) ||
+        (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&d_err, 1)) || (e = dalloc(&ix->d_map, 256)) ||
+        (e = ix->words.alloc(n_words, nbytes, ix->kind, true, true))) {
+        cleanup();
+        fpm_index_destroy(ix);
+        return hip_fail(e, "fpm_build_fingerprints alloc");
+    }
+    if (nbytes)
+        (void)hipMemcpyAsync(d_bytes, bytes, nbytes, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(d_off, offsets, sizeof(uint64_t) * ((size_t)n_words + 1), hipMemcpyHostToDevice, s);
+    launch_zero(d_err, 1, s);
+    if (symbols == FPM_CUSTOM) {
+        (void)hipMemcpyAsync(ix->d_map, custom_map, 256, hipMemcpyHostToDevice, s);
+    } else {
+        launch_zero(d_hist, 512, s);
+        launch_byte_histogram(d_bytes, d_off, n_words, d_hist, s);
+        launch_select_symbols(d_hist, nf, (int)symbols, ix->d_map, s);
+    }
+    prep_strings(ix->words, d_bytes, d_off, n_words, nbytes, ix->d_map, variant, bits, ix->kind, true, d_err, scratch,
+                 s);
+    launch_invert(ix->words.perm, n_words, ix->words.inv, s);
+    (void)hipMemcpyAsync(ix->map, ix->d_map, 256, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(ix->h_off, ix->words.off, sizeof(uint32_t) * 257, hipMemcpyDeviceToHost, s);
+    e = hipStreamSynchronize(s);
+    if (!e)
+        e = hipGetLastError();
+    cleanup();
+    if (e) {
+        fpm_index_destroy(ix);
+        return hip_fail(e, "fpm_build_fingerprints");
+    }
+    *out = ix;
+    return FPM_OK;
+}
+
+fpm_status fpm_get_fingerprints(const fpm_index *ix, uint32_t *out)
+{
+    g_last_error.clear();
+    if (!ix || (!out && ix->n))
+        return fail(FPM_EINVAL, "null pointer");
+    if (ix->n)
+        HIPCHK(hipMemcpy(out, ix->words.fp_orig, sizeof(uint32_t) * ix->n, hipMemcpyDeviceToHost));
+    return FPM_OK;
+}
+
+fpm_status fpm_get_map(const fpm_index *ix, uint8_t map_out[256])
+{
+    g_last_error.clear();
+    if (!ix || !map_out)
+        return fail(FPM_EINVAL, "null pointer");
+    memcpy(map_out, ix->map, 256);
+    return FPM_OK;
+}
+
+fpm_status fpm_index_info(const fpm_index *ix, uint32_t *n_words, uint32_t *variant, uint32_t *bits)
+{
+    g_last_error.clear();
+    if (!ix)
+        return fail(FPM_EINVAL, "null index");
+    if (n_words)
+        *n_words = ix->n;
+    if (variant)
+        *variant = (uint32_t)ix->variant;
+    if (bits)
+        *bits = ix->bits;
+    return FPM_OK;
+}
+
+// ---------------------------------------------------------------- plans
+
+static void plan_free(fpm_plan *p)
+{
+    if (!p)
+        return;
+    if (p->gexec)
+        (void)hipGraphExecDestroy(p->gexec);
+    p->q.release();
+    dfree(p->scratch);
+    dfree(p->pairs);
+    dfree(p->ctr);
+    dfree(p->keys);
+    dfree(p->tmp);
+    dfree(p->triples);
+    if (p->ev0)
+        (void)hipEventDestroy(p->ev0);
+    if (p->ev1)
+        (void)hipEventDestroy(p->ev1);
+    if (p->own_stream && p->stream)
+        (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+void fpm_plan_destroy(fpm_plan *plan) { plan_free(plan); }
+
+static fpm_status check_metric(const fpm_index *ix, fpm_metric metric, uint32_t k)
+{
+    if (metric != FPM_HAM && metric != FPM_LEV)
+        return fail(FPM_EINVAL, "unknown metric %d", (int)metric);
+    if (k < 1 || k > 2)
+        return fail(FPM_EUNSUPPORTED, "k = %u: the GPU matcher supports k = 1 and k = 2", k);
+    if (metric == FPM_LEV && (ix->variant == FPM_POS || ix->variant == FPM_OCCH))
+        return fail(FPM_EUNSUPPORTED, "position and occurrence-halved fingerprints are sound for Hamming only");
+    return FPM_OK;
+}
+
+static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
+{
+    memset(o, 0, sizeof(*o));
+    if (in)
+        *o = *in;
+    if (o->schedule > FPM_SCHED_BRUTE)
+        return fail(FPM_EINVAL, "unknown schedule %u", o->schedule);
+    if (!o->queries_per_item)
+        o->queries_per_item = 64;
+    if (!o->slab)
+        o->slab = 16384;
+    if (!o->use_graph)
+        o->use_graph = 1;
+    if (!o->waves_per_cu)
+        o->waves_per_cu = 16;
+    if (!o->match_capacity)
+        o->match_capacity = 1u << 20;
+    if (o->queries_per_item % 16 || o->queries_per_item > 1024)
+        return fail(FPM_EINVAL, "queries_per_item must be a multiple of 16 up to 1024");
+    if (o->slab % 64 || o->slab < 64 || o->slab > (1u << 24))
+        return fail(FPM_EINVAL, "slab must be a multiple of 64 in 64..16M");
+    if (o->bucket_order > 1)
+        return fail(FPM_EINVAL, "bucket_order must be 0 or 1");
+    if (o->waves_per_cu > 64)
+        return fail(FPM_EINVAL, "waves_per_cu must be <= 64");
+    return FPM_OK;
+}
+
+static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_t max_query_bytes, fpm_metric metric,
+                              uint32_t k, const fpm_options *opt, void *hip_stream, bool survivors_only,
+                              fpm_plan **out)
+{
+    if (!out)
+        return fail(FPM_EINVAL, "null out");
+    *out = nullptr;
+    if (!ix)
+        return fail(FPM_EINVAL, "null index");
+    fpm_status st = check_metric(ix, metric, k);
+    if (st)
+        return st;
+    if (max_queries >= (1u << 30))
+        return fail(FPM_EINVAL, "max_queries must be below 2^30");
+    if (bits_for(std::max<uint32_t>(max_queries, 1)) + ix->wbits + 2 > 64)
+        return fail(FPM_EINVAL, "query and word index bits exceed the 64-bit match key");
+    fpm_plan *p = new (std::nothrow) fpm_plan();
+    if (!p)
+        return fail(FPM_ENOMEM, "host allocation");
+    st = resolve_options(opt, &p->opt);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->ix = ix;
+    p->max_q = max_queries;
+    p->max_bytes = max_query_bytes;
+    p->metric = metric;
+    p->k = k;
+    p->survivors_only = survivors_only;
+    p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : ix->kind;
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        p->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        p->own_stream = true;
+    }
+    const int qkind = p->kind == kAll ? kPop32 : p->kind;
+    if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false)) ||
+        (e = dalloc(&p->scratch, 256u * kRadixBlocks)) || (e = dalloc(&p->pairs, kMaxPairs)) ||
+        (e = dalloc(&p->ctr, 1)) || (e = hipEventCreate(&p->ev0)) || (e = hipEventCreate(&p->ev1))) {
+        plan_free(p);
+        return hip_fail(e, "fpm_plan_create alloc");
+    }
+    st = p->alloc_output(p->opt.match_capacity);
+    if (st) {
+        plan_free(p);
+        return st;
+    }
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    p->persistent_blocks = std::max(1, cus * (int)p->opt.waves_per_cu / 4);
+    p->h_pairs.resize(kMaxPairs);
+    *out = p;
+    return FPM_OK;
+}
+
+fpm_status fpm_plan_create(const fpm_index *ix, uint32_t max_queries, uint64_t max_query_bytes, fpm_metric metric,
+                           uint32_t k, const fpm_options *opt, void *hip_stream, fpm_plan **out)
+{
+    g_last_error.clear();
+    return plan_create(ix, max_queries, max_query_bytes, metric, k, opt, hip_stream, false, out);
+}
+
+// Everything of one match that runs on the device.  With `plain` the
+// host reads the query bucket table in the middle (one synchronisation).
+static fpm_status plan_enqueue(fpm_plan *p, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t nq,
+                               bool plain)
+{
+    const fpm_index *ix = p->ix;
+    hipStream_t s = p->stream;
+    launch_zero(p->ctr, sizeof(DevCounters) / 4, s);
+    const bool fps = p->kind != kAll;
+    prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
+                 fps ? p->kind : kPop32, fps, &p->ctr->err, p->scratch, s);
+    WorkList wl{p->pairs, &p->ctr->n_pairs, &p->ctr->n_items, &p->ctr->counter, &p->ctr->examined};
+    if (plain) {
+        uint32_t h_qoff[257];
+        HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        uint32_t np = 0;
+        p->host_items = host_worklist(h_qoff, ix->h_off, p->metric, p->k, p->opt.queries_per_item, p->opt.slab,
+                                      p->opt.bucket_order, p->h_pairs.data(), &np, &p->host_examined);
+        struct {
+            uint32_t n_pairs, n_items;
+        } hdr{np, p->host_items};
+        if (np)
+            HIPCHK(hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(PairRec) * np, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(&p->ctr->n_pairs, &hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(&p->ctr->examined, &p->host_examined, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        // the copies read host stack memory: finish them before returning
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        launch_worklist(p->q.off, ix->words.off, p->metric, p->k, p->opt.queries_per_item, p->opt.slab,
+                        p->opt.bucket_order, wl, s);
+    }
+    MatchArgs a;
+    a.q = p->q.view();
+    a.d = ix->words.view();
+    a.wl = wl;
+    a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells};
+    a.out_keys = p->keys;
+    a.out_cap = p->cap;
+    a.qtile = p->opt.queries_per_item;
+    a.slab = p->opt.slab;
+    a.wbits = ix->wbits;
+    a.survivors_only = p->survivors_only ? 1u : 0u;
+    hipError_t e = launch_match(a, p->kind, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks, p->host_items, s);
+    if (e)
+        return hip_fail(e, "match kernel launch");
+    const uint32_t qbits = bits_for(std::max<uint32_t>(nq, 1));
+    launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, s);
+    launch_unpack(p->keys, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, s);
+    return FPM_OK;
+}
+
+static fpm_status plan_launch(fpm_plan *p, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t nq)
+{
+    hipStream_t s = p->stream;
+    const bool plain = p->opt.schedule != FPM_SCHED_BATCHED;
+    const bool graph = !plain && p->opt.use_graph == 1;
+    HIPCHK(hipEventRecord(p->ev0, s));
+    if (graph) {
+        if (!p->gexec || p->g_bytes != d_qbytes || p->g_offsets != d_qoffsets || p->g_nq != nq) {
+            if (p->gexec) {
+                (void)hipGraphExecDestroy(p->gexec);
+                p->gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            fpm_status st = plan_enqueue(p, d_qbytes, d_qoffsets, nq, false);
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e)
+                return hip_fail(e, "graph capture");
+            e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e)
+                return hip_fail(e, "graph instantiate");
+            p->g_bytes = d_qbytes;
+            p->g_offsets = d_qoffsets;
+            p->g_nq = nq;
+        }
+        HIPCHK(hipGraphLaunch(p->gexec, s));
+    } else {
+        fpm_status st = plan_enqueue(p, d_qbytes, d_qoffsets, nq, plain);
+        if (st)
+            return st;
+    }
+    HIPCHK(hipEventRecord(p->ev1, s));
+    return FPM_OK;
+}
+
+fpm_status fpm_plan_run(fpm_plan *p, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t n_queries)
+{
+    g_last_error.clear();
+    if (!p)
+        return fail(FPM_EINVAL, "null plan");
+    if (n_queries > p->max_q)
+        return fail(FPM_EINVAL, "%u queries exceed the plan's %u", n_queries, p->max_q);
+    if (n_queries && (!d_qoffsets || (!d_qbytes && p->max_bytes)))
+        return fail(FPM_EINVAL, "null query pointer");
+    p->last_bytes = d_qbytes;
+    p->last_offsets = d_qoffsets;
+    p->last_nq = n_queries;
+    p->ran = true;
+    if (n_queries == 0)
+        return FPM_OK;
+    return plan_launch(p, d_qbytes, d_qoffsets, n_queries);
+}
+
+fpm_status fpm_plan_result(fpm_plan *p, const fpm_hit **d_matches, uint64_t *n_out, fpm_stats *stats)
+{
+    g_last_error.clear();
+    if (!p || !p->ran)
+        return fail(FPM_EINVAL, "plan has not run");
+    fpm_stats st;
+    memset(&st, 0, sizeof(st));
+    st.pairs_logical = (uint64_t)p->last_nq * p->ix->n;
+    if (p->last_nq == 0) {
+        if (d_matches)
+            *d_matches = (const fpm_hit *)p->triples;
+        if (n_out)
+            *n_out = 0;
+        if (stats)
+            *stats = st;
+        return FPM_OK;
+    }
+    DevCounters c;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        HIPCHK(hipStreamSynchronize(p->stream));
+        HIPCHK(hipMemcpy(&c, p->ctr, sizeof(c), hipMemcpyDeviceToHost));
+        if (c.err)
+            return fail(FPM_EINVAL, "query batch: %s",
+                        (c.err & 2) ? "offsets decrease"
+                                    : (c.err & 1) ? "a string is longer than 255" : "more bytes than max_query_bytes");
+        if (c.n_out <= p->cap)
+            break;
+        // the match buffer overflowed: grow it and run again
+        fpm_status s2 = p->alloc_output(c.n_out + c.n_out / 4 + 1024);
+        if (s2)
+            return s2;
+        s2 = plan_launch(p, p->last_bytes, p->last_offsets, p->last_nq);
+        if (s2)
+            return s2;
+    }
+    if (c.n_out > p->cap)
+        return fail(FPM_EDEVICE, "match buffer overflow persists");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
+    st.pairs_examined = c.examined;
+    st.survivors = c.survivors;
+    st.matches = c.n_out;
+    st.verify_cells = c.cells;
+    st.ms = ms;
+    st.work_items = c.n_items;
+    if (d_matches)
+        *d_matches = (const fpm_hit *)p->triples;
+    if (n_out)
+        *n_out = c.n_out;
+    if (stats)
+        *stats = st;
+    return FPM_OK;
+}
+
+fpm_status fpm_plan_copy_matches(fpm_plan *p, fpm_hit *dst, uint64_t max, uint64_t *n_copied)
+{
+    g_last_error.clear();
+    const fpm_hit *dm = nullptr;
+    uint64_t n = 0;
+    fpm_status st = fpm_plan_result(p, &dm, &n, nullptr);
+    if (st)
+        return st;
+    n = std::min(n, max);
+    if (n) {
+        if (!dst)
+            return fail(FPM_EINVAL, "null destination");
+        HIPCHK(hipMemcpy(dst, dm, sizeof(fpm_hit) * n, hipMemcpyDefault));
+    }
+    if (n_copied)
+        *n_copied = n;
+    return FPM_OK;
+}
+
+// Host-buffer convenience path: one temporary plan per call.
+static fpm_status match_host(const fpm_index *ix, const uint8_t *qbytes, const uint64_t *qoffsets, uint32_t nq,
+                             fpm_metric metric, uint32_t k, const fpm_options *opt, bool survivors_only,
+                             uint32_t **out, uint64_t *n_out, fpm_stats *stats)
+{
+    if (!ix || !out || !n_out)
+        return fail(FPM_EINVAL, "null pointer");
+    *out = nullptr;
+    *n_out = 0;
+    fpm_status st = check_metric(ix, metric, k);
+    if (st)
+        return st;
+    st = check_csr(qbytes, qoffsets, nq, "queries");
+    if (st)
+        return st;
+    const uint64_t nbytes = nq ? qoffsets[nq] : 0;
+    fpm_plan *p = nullptr;
+    st = plan_create(ix, std::max<uint32_t>(nq, 1), nbytes + 4, metric, k, opt, nullptr, survivors_only, &p);
+    if (st)
+        return st;
+    uint8_t *d_b = nullptr;
+    uint64_t *d_o = nullptr;
+    hipError_t e;
+    if ((e = dalloc(&d_b, nbytes + 4)) || (e = dalloc(&d_o, (size_t)nq + 1))) {
+        dfree(d_b);
+        plan_free(p);
+        return hip_fail(e, "query upload alloc");
+    }
+    if (nbytes)
+        (void)hipMemcpyAsync(d_b, qbytes, nbytes, hipMemcpyHostToDevice, p->stream);
+    if (nq)
+        (void)hipMemcpyAsync(d_o, qoffsets, sizeof(uint64_t) * ((size_t)nq + 1), hipMemcpyHostToDevice, p->stream);
+    st = fpm_plan_run(p, d_b, d_o, nq);
+    const fpm_hit *dm = nullptr;
+    uint64_t n = 0;
+    if (!st)
+        st = fpm_plan_result(p, &dm, &n, stats);
+    if (!st && n) {
+        const size_t width = survivors_only ? 2 : 3;
+        uint32_t *h = (uint32_t *)malloc(sizeof(uint32_t) * width * n);
+        if (!h) {
+            st = fail(FPM_ENOMEM, "host result allocation");
+        } else if ((e = hipMemcpy(h, dm, sizeof(uint32_t) * width * n, hipMemcpyDeviceToHost))) {
+            free(h);
+            st = hip_fail(e, "result copy");
+        } else {
+            *out = h;
+            *n_out = n;
+        }
+    }
+    dfree(d_b);
+    dfree(d_o);
+    plan_free(p);
+    return st;
+}
+
+fpm_status fpm_match(const fpm_index *ix, const uint8_t *qbytes, const uint64_t *qoffsets, uint32_t n_queries,
+                     fpm_metric metric, uint32_t k, const fpm_options *opt, fpm_hit **out, uint64_t *n_out,
+                     fpm_stats *stats)
+{
+    g_last_error.clear();
+    return match_host(ix, qbytes, qoffsets, n_queries, metric, k, opt, false, (uint32_t **)out, n_out, stats);
+}
+
+fpm_status fpm_filter_pairs(const fpm_index *ix, const uint8_t *qbytes, const uint64_t *qoffsets,
+                            uint32_t n_queries, fpm_metric metric, uint32_t k, uint32_t **pairs, uint64_t *n_pairs)
+{
+    g_last_error.clear();
+    fpm_options o;
+    memset(&o, 0, sizeof(o));
+    o.schedule = FPM_SCHED_PLAIN;
+    return match_host(ix, qbytes, qoffsets, n_queries, metric, k, &o, true, pairs, n_pairs, nullptr);
+}
+
+// Temporary device copy of host strings, sorted and fingerprinted.
+struct TmpSet {
+    StrSet S;
+    uint8_t *b = nullptr;
+    uint64_t *o = nullptr;
+    uint32_t *scratch = nullptr, *err = nullptr;
+    hipStream_t s = nullptr;
+    ~TmpSet()
+    {
+        S.release();
+        dfree(b);
+        dfree(o);
+        dfree(scratch);
+        dfree(err);
+        if (s)
+            (void)hipStreamDestroy(s);
+    }
+    fpm_status make(const fpm_index *ix, const uint8_t *bytes, const uint64_t *offsets, uint32_t n, bool fp_orig)
+    {
+        const uint64_t nbytes = offsets[n];
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&b, nbytes + 4)) ||
+            (e = dalloc(&o, (size_t)n + 1)) || (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&err, 1)) ||
+            (e = S.alloc(n, nbytes + 4, ix->kind, fp_orig, true)))
+            return hip_fail(e, "temporary string set");
+        if (nbytes)
+            (void)hipMemcpyAsync(b, bytes, nbytes, hipMemcpyHostToDevice, s);
+        (void)hipMemcpyAsync(o, offsets, sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s);
+        launch_zero(err, 1, s);
+        prep_strings(S, b, o, n, nbytes, ix->d_map, ix->variant, ix->bits, ix->kind, true, err, scratch, s);
+        launch_invert(S.perm, n, S.inv, s);
+        return FPM_OK;
+    }
+};
+
+fpm_status fpm_fingerprints(const fpm_index *ix, const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
+                            uint32_t *out)
+{
+    g_last_error.clear();
+    if (!ix || (n && !out))
+        return fail(FPM_EINVAL, "null pointer");
+    fpm_status st = check_csr(bytes, offsets, n, "strings");
+    if (st || n == 0)
+        return st;
+    TmpSet t;
+    st = t.make(ix, bytes, offsets, n, true);
+    if (st)
+        return st;
+    HIPCHK(hipMemcpyAsync(out, t.S.fp_orig, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, t.s));
+    HIPCHK(hipStreamSynchronize(t.s));
+    return FPM_OK;
+}
+
+fpm_status fpm_verify_pairs(const fpm_index *ix, const uint8_t *qbytes, const uint64_t *qoffsets, uint32_t n_queries,
+                            const uint32_t *pairs, uint64_t n_pairs, fpm_metric metric, uint32_t k, uint32_t *dist_out)
+{
+    g_last_error.clear();
+    if (!ix || (n_pairs && (!pairs || !dist_out)))
+        return fail(FPM_EINVAL, "null pointer");
+    if (metric != FPM_HAM && metric != FPM_LEV)
+        return fail(FPM_EINVAL, "unknown metric");
+    if (k < 1 || k > 2)
+        return fail(FPM_EUNSUPPORTED, "k must be 1 or 2");
+    fpm_status st = check_csr(qbytes, qoffsets, n_queries, "queries");
+    if (st || n_pairs == 0)
+        return st;
+    for (uint64_t i = 0; i < n_pairs; ++i)
+        if (pairs[2 * i] >= n_queries || pairs[2 * i + 1] >= ix->n)
+            return fail(FPM_EINVAL, "pair %llu out of range", (unsigned long long)i);
+    TmpSet t;
+    st = t.make(ix, qbytes, qoffsets, n_queries, false);
+    if (st)
+        return st;
+    uint32_t *d_pairs = nullptr, *d_dist = nullptr;
+    hipError_t e;
+    if ((e = dalloc(&d_pairs, 2 * n_pairs)) || (e = dalloc(&d_dist, n_pairs))) {
+        dfree(d_pairs);
+        return hip_fail(e, "verify alloc");
+    }
+    (void)hipMemcpyAsync(d_pairs, pairs, sizeof(uint32_t) * 2 * n_pairs, hipMemcpyHostToDevice, t.s);
+    e = launch_verify_pairs(t.S.view(), t.S.inv, ix->words.view(), ix->words.inv, d_pairs, n_pairs, metric, k, d_dist,
+                            t.s);
+    if (!e)
+        e = hipMemcpyAsync(dist_out, d_dist, sizeof(uint32_t) * n_pairs, hipMemcpyDeviceToHost, t.s);
+    if (!e)
+        e = hipStreamSynchronize(t.s);
+    dfree(d_pairs);
+    dfree(d_dist);
+    if (e)
+        return hip_fail(e, "fpm_verify_pairs");
+    return FPM_OK;
+}
+
+fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t n_queries,
+                        uint64_t query_bytes, fpm_metric metric, uint32_t k, uint32_t repeats, fpm_options *best,
+                        float *timings_out, uint32_t max_timings, uint32_t *n_timings)
+{
+    g_last_error.clear();
+    if (!ix || !best)
+        return fail(FPM_EINVAL, "null pointer");
+    static const uint32_t qts[] = {16, 32, 64, 128, 256};
+    static const uint32_t slabs[] = {4096, 8192, 16384, 32768, 65536};
+    if (repeats == 0)
+        repeats = 3;
+    fpm_options base = *best;
+    float best_ms = 1e30f;
+    uint32_t nt = 0;
+    for (uint32_t order = 0; order < 2; ++order) {
+        for (uint32_t qt : qts) {
+            for (uint32_t sl : slabs) {
+                fpm_options o = base;
+                o.schedule = FPM_SCHED_BATCHED;
+                o.queries_per_item = qt;
+                o.slab = sl;
+                o.bucket_order = order;
+                if (!o.use_graph)
+                    o.use_graph = 1;
+                fpm_plan *p = nullptr;
+                fpm_status st = plan_create(ix, n_queries, query_bytes, metric, k, &o, nullptr, false, &p);
+                if (st)
+                    return st;
+                float tot = 0.f;
+                for (uint32_t r = 0; r <= repeats && !st; ++r) {
+                    st = fpm_plan_run(p, d_qbytes, d_qoffsets, n_queries);
+                    fpm_stats s;
+                    if (!st)
+                        st = fpm_plan_result(p, nullptr, nullptr, &s);
+                    if (!st && r > 0)
+                        tot += s.ms;
+                }
+                if (!st)
+                    o.match_capacity = (uint32_t)std::min<uint64_t>(p->cap, 0xFFFFFFFFu);
+                plan_free(p);
+                if (st)
+                    return st;
+                const float ms = tot / repeats;
+                if (timings_out && nt < max_timings) {
+                    timings_out[4 * nt + 0] = (float)qt;
+                    timings_out[4 * nt + 1] = (float)sl;
+                    timings_out[4 * nt + 2] = (float)order;
+                    timings_out[4 * nt + 3] = ms;
+                }
+                ++nt;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    *best = o;
+                }
+            }
+        }
+    }
+    if (n_timings)
+        *n_timings = std::min(nt, max_timings);
+    return FPM_OK;
+}
+
+}  // extern "C"

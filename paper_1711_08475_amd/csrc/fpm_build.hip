@@ -1,0 +1,305 @@
+// fpm_build.hip -- preprocessing kernels: symbol statistics and selection
+// (Section 3: common / rare / mixed symbol sets), length bucketing into
+// padded blocks, and fingerprint construction (Section 3.2).
+#include "fpm_internal.hpp"
+
+namespace fpm {
+
+namespace {
+
+__global__ void k_zero(uint32_t *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_lengths(const uint64_t *offsets, uint32_t n, uint32_t *len_out, uint32_t *err)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint64_t a = offsets[i], b = offsets[i + 1];
+    uint32_t L;
+    if (b < a) {
+        atomicOr(err, 2u);
+        L = 0;
+    } else if (b - a > (uint64_t)kMaxLen) {
+        atomicOr(err, 1u);
+        L = kMaxLen;
+    } else {
+        L = (uint32_t)(b - a);
+    }
+    len_out[i] = L;
+}
+
+__global__ void __launch_bounds__(256) k_byte_hist(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
+                                                   unsigned long long *hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t lo = offsets[0], hi = offsets[n];
+    for (uint64_t i = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < hi;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[bytes[i]], 1u);
+    __syncthreads();
+    if (h[threadIdx.x])
+        atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// Symbol selection.  Thread c ranks byte c among the symbols that occur:
+// descending rank orders by (count desc, byte asc), ascending rank by
+// (count asc, byte asc).  common: field = descending rank < F; rare: field
+// = ascending rank < F; mixed: the ceil(F/2) first in descending order, then
+// the remaining symbols in ascending order until F fields are used.
+__global__ void __launch_bounds__(256) k_select(const unsigned long long *hist, int nf, int symset, uint8_t *map)
+{
+    __shared__ unsigned long long h[256];
+    __shared__ uint32_t rdesc[256];
+    __shared__ uint32_t npresent;
+    const uint32_t c = threadIdx.x;
+    h[c] = hist[c];
+    if (c == 0)
+        npresent = 0;
+    __syncthreads();
+    const bool present = h[c] > 0;
+    if (present)
+        atomicAdd(&npresent, 1u);
+    uint32_t rd = 0, ra = 0;
+    for (uint32_t o = 0; o < 256; ++o) {
+        if (h[o] == 0)
+            continue;
+        rd += (h[o] > h[c] || (h[o] == h[c] && o < c)) ? 1u : 0u;
+        ra += (h[o] < h[c] || (h[o] == h[c] && o < c)) ? 1u : 0u;
+    }
+    rdesc[c] = present ? rd : 0xFFFFFFFFu;
+    __syncthreads();
+    uint32_t field = 0xFFu;
+    if (present) {
+        if (symset == 0) {
+            if (rd < (uint32_t)nf)
+                field = rd;
+        } else if (symset == 1) {
+            if (ra < (uint32_t)nf)
+                field = ra;
+        } else {
+            const uint32_t hc = (uint32_t)(nf + 1) / 2;
+            if (rd < hc) {
+                field = rd;
+            } else {
+                const uint32_t ncommon = min(hc, npresent);
+                uint32_t rr = 0;  // rank among the not-yet-chosen symbols, ascending order
+                for (uint32_t o = 0; o < 256; ++o) {
+                    if (h[o] == 0 || rdesc[o] < hc)
+                        continue;
+                    rr += (h[o] < h[c] || (h[o] == h[c] && o < c)) ? 1u : 0u;
+                }
+                if (ncommon + rr < (uint32_t)nf)
+                    field = ncommon + rr;
+            }
+        }
+    }
+    map[c] = (uint8_t)field;
+}
+
+// A string whose slot would end beyond str_cap dwords (possible only when a
+// caller's query bytes exceed the capacity it declared) becomes the empty
+// string at offset 0 and err gets bit 4.
+__global__ void k_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit, const uint32_t *perm,
+                         const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
+                         uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint32_t i = perm[p];
+    uint32_t L = len[i];
+    uint32_t sw = slot_dwords(L);
+    uint32_t so = bdw[L] + (p - off[L]) * sw;
+    if ((uint64_t)so + sw > str_cap) {
+        atomicOr(err, 4u);
+        slen[p] = 0;
+        soff[p] = 0;
+        return;
+    }
+    slen[p] = (uint8_t)L;
+    soff[p] = so;
+    const uint64_t start = offsets[i];
+    const uint64_t end_all = offsets[n];
+    const uint64_t limit = end_all < nbytes_limit ? end_all : nbytes_limit;
+    for (uint32_t t = 0; t < sw; ++t) {
+        uint32_t w = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t pos = 4 * t + j;
+            const uint64_t a = start + pos;
+            if (pos < L && a < limit)
+                w |= (uint32_t)bytes[a] << (8 * j);
+        }
+        str[so + t] = w;
+    }
+}
+
+// Fingerprint of one padded string (Section 3.2).  Field f of the map:
+//   occ  -> bit f;
+//   occh -> bit 2f for a symbol in the first floor(L/2) positions, 2f+1 after;
+//   count-> 2-bit saturating counter at bits 2f, 2f+1;
+//   pos  -> f < npos: first position (0-indexed) in 3 bits at 3f, all ones
+//           when it is >= 7 or the symbol is absent; f >= npos: occurrence
+//           bit 3*npos + (f - npos).
+template <int VARIANT>
+__device__ __forceinline__ uint32_t fingerprint(const uint32_t *s, uint32_t L, const uint8_t *smap, uint32_t npos)
+{
+    uint32_t fp = 0;
+    if (VARIANT == 2)
+        fp = (npos == 10) ? 0x3FFFFFFFu : 0x7FFFu;  // every position field starts at all ones
+    const uint32_t half = L >> 1;
+    const uint32_t nw = (L + 3) >> 2;
+    for (uint32_t t = 0; t < nw; ++t) {
+        const uint32_t w = s[t];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t pos = 4 * t + j;
+            if (pos >= L)
+                break;
+            const uint32_t f = smap[(w >> (8 * j)) & 0xFFu];
+            if (f == 0xFFu)
+                continue;
+            if (VARIANT == 0) {
+                fp |= 1u << f;
+            } else if (VARIANT == 3) {
+                fp |= 1u << (2 * f + (pos >= half ? 1u : 0u));
+            } else if (VARIANT == 1) {
+                if (((fp >> (2 * f)) & 3u) != 3u)
+                    fp += 1u << (2 * f);
+            } else {
+                if (f < npos) {
+                    if (pos < 7 && ((fp >> (3 * f)) & 7u) == 7u)
+                        fp = (fp & ~(7u << (3 * f))) | (pos << (3 * f));
+                } else {
+                    fp |= 1u << (3 * npos + (f - npos));
+                }
+            }
+        }
+    }
+    return fp;
+}
+
+template <int VARIANT>
+__global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_t *slen,
+                                                      const uint32_t *perm, uint32_t n, const uint8_t *map, int bits,
+                                                      uint32_t *fp_sorted, uint32_t *fp_orig, void *keys,
+                                                      int key_kind)
+{
+    __shared__ uint8_t smap[256];
+    smap[threadIdx.x] = map[threadIdx.x];
+    __syncthreads();
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint32_t npos = (uint32_t)bits / 3;
+    const uint32_t fp = fingerprint<VARIANT>(str + soff[p], slen[p], smap, npos);
+    if (fp_sorted)
+        fp_sorted[p] = fp;
+    if (fp_orig)
+        fp_orig[perm[p]] = fp;
+    if (!keys)
+        return;
+    if (VARIANT == 1) {
+        // thermometer expansion of each 2-bit count v: [v>=1, v>=2, v>=3];
+        // the popcount of the XOR of two expansions is the L1 distance of
+        // the counts.
+        const uint32_t lo = fp & 0x55555555u, hi = (fp >> 1) & 0x55555555u;
+        const uint32_t t0 = lo | hi, t1 = hi, t2 = lo & hi;
+        if (key_kind == kPop64) {
+            ((uint64_t *)keys)[p] = (uint64_t)(t0 | (t1 << 1)) | ((uint64_t)t2 << 32);
+        } else {
+            ((uint32_t *)keys)[p] = (t0 | (t1 << 1)) | (t2 << 16);  // 8 fields: bits 0..15 and 16..30
+        }
+    } else {
+        ((uint32_t *)keys)[p] = fp;
+    }
+}
+
+__global__ void k_invert(const uint32_t *perm, uint32_t n, uint32_t *inv)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n)
+        inv[perm[p]] = p;
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_zero(void *p, size_t n_u32, hipStream_t s)
+{
+    if (n_u32 == 0)
+        return;
+    uint32_t blocks = (uint32_t)std::min<size_t>(1024, (n_u32 + 255) / 256);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (uint32_t *)p, n_u32);
+}
+
+void launch_lengths(const uint64_t *offsets, uint32_t n, uint32_t *len_out, uint32_t *err, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    hipLaunchKernelGGL(k_lengths, dim3(blocks_for(n, 256)), dim3(256), 0, s, offsets, n, len_out, err);
+}
+
+void launch_byte_histogram(const uint8_t *bytes, const uint64_t *offsets, uint32_t n, unsigned long long *hist,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_byte_hist, dim3(1024), dim3(256), 0, s, bytes, offsets, n, hist);
+}
+
+void launch_select_symbols(const unsigned long long *hist, int nfields, int symset, uint8_t *map_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, hist, nfields, symset, map_out);
+}
+
+void launch_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit, const uint32_t *perm,
+                   const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
+                   uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    hipLaunchKernelGGL(k_layout, dim3(blocks_for(n, 256)), dim3(256), 0, s, bytes, offsets, nbytes_limit, perm, len,
+                       off, bdw, n, slen, soff, str, str_cap, err);
+}
+
+void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_t *slen, const uint32_t *perm,
+                         uint32_t n, const uint8_t *map, int variant, int bits, uint32_t *fp_sorted,
+                         uint32_t *fp_orig, void *keys, int key_kind, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    dim3 g(blocks_for(n, 256)), b(256);
+    switch (variant) {
+    case 0:
+        hipLaunchKernelGGL(k_fingerprints<0>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
+                           keys, key_kind);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_fingerprints<1>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
+                           keys, key_kind);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_fingerprints<2>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
+                           keys, key_kind);
+        break;
+    default:
+        hipLaunchKernelGGL(k_fingerprints<3>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
+                           keys, key_kind);
+        break;
+    }
+}
+
+void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, inv);
+}
+
+}  // namespace fpm

@@ -1,0 +1,145 @@
+// fpm_internal.hpp -- internal declarations shared by the HIP sources of
+// libfpm (device-side data layout, kernel launch wrappers).
+//
+// Device layout of a string set (dictionary or query batch), all in HBM:
+//   * strings are stably sorted by length; strings of length L occupy the
+//     sorted positions [off[L], off[L+1]);
+//   * each string is copied into a zero-padded slot of sw(L) = max(1,
+//     ceil(L/4)) dwords; the slots of one length form one dense block;
+//     soff[p] is the dword offset of sorted string p, len[p] its length and
+//     perm[p] its position in the caller's list;
+//   * key[p] is the filter key of string p (see fpm_match.hip): the
+//     fingerprint itself, or for the count variant its thermometer
+//     expansion, so that one XOR and one popcount give F_D.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fpm {
+
+constexpr int kMaxLen = 255;
+constexpr int kBuckets = 256;        // lengths 0..255
+constexpr int kMaxPairs = 256 * 5;   // (query length, word length) pairs, |dL| <= 2
+constexpr int kRadixBlocks = 256;    // blocks of one stable radix pass
+
+__host__ __device__ inline uint32_t slot_dwords(uint32_t len) { return len == 0 ? 1u : (len + 3u) >> 2; }
+
+// Filter-key families.  Pop32: F_D = popc(kq ^ kw) on 32-bit keys (occ,
+// occ-halved, 16-bit count thermometer); Pop64: the same on 64-bit keys
+// (32-bit count thermometer); Pos16 / Pos32: position fingerprints; All: no
+// filter (brute force, every length-compatible pair is verified).
+enum KeyKind : int { kPop32 = 0, kPop64 = 1, kPos16 = 2, kPos32 = 3, kAll = 4 };
+
+struct StrSetView {
+    const uint32_t *perm;  // sorted -> caller index
+    const uint8_t *len;    // sorted -> length
+    const uint32_t *soff;  // sorted -> dword offset of the padded string
+    const uint32_t *str;   // padded strings
+    const uint32_t *off;   // [257] bucket offsets
+    const void *key;       // filter keys (uint32 or uint64), sorted order
+};
+
+// One (query length, word length) pair of buckets and its work items.
+struct PairRec {
+    uint32_t item_base;  // first work item of this pair
+    uint32_t qbase, nq;  // sorted query range
+    uint32_t dbase, nd;  // sorted dictionary range
+    uint32_t tiles_d;    // dictionary slabs per query tile
+    uint32_t qlen, dlen;
+};
+
+struct WorkList {
+    PairRec *pairs;       // [kMaxPairs]
+    uint32_t *n_pairs;    // device scalar
+    uint32_t *n_items;    // device scalar
+    uint32_t *counter;    // persistent work counter
+    uint64_t *examined;   // device scalar: length-compatible pairs
+};
+
+struct MatchCounters {
+    uint64_t *n_out;        // matches found (may exceed capacity)
+    uint64_t *survivors;    // pairs verified
+    uint64_t *verify_cells; // sum (2k+1) * min(m, n)
+};
+
+struct MatchArgs {
+    StrSetView q, d;
+    WorkList wl;
+    MatchCounters ctr;
+    uint64_t *out_keys;   // packed (query, word, dist) keys
+    uint64_t out_cap;
+    uint32_t qtile;       // queries per work item
+    uint32_t slab;        // words per work item
+    uint32_t wbits;       // bits of a word index in the packed key
+    uint32_t survivors_only;  // 1: report every survivor with dist 0, no verification
+};
+
+// ----------------------------------------------------------------- build
+// Lengths of a CSR list, clamped to kMaxLen; err gets bit 1 for a long
+// string, bit 2 for decreasing offsets.  Reads offsets[0..n].
+void launch_lengths(const uint64_t *offsets, uint32_t n, uint32_t *len_out, uint32_t *err, hipStream_t s);
+
+// Byte histogram of bytes[offsets[0] .. offsets[n]) into hist[256].
+void launch_byte_histogram(const uint8_t *bytes, const uint64_t *offsets, uint32_t n, unsigned long long *hist,
+                           hipStream_t s);
+// Symbol map from a histogram (common / rare / mixed), map_out[256].
+void launch_select_symbols(const unsigned long long *hist, int nfields, int symset, uint8_t *map_out, hipStream_t s);
+
+// Stable sort of indices 0..n-1 by length (a single 8-bit radix pass).
+// Writes perm (sorted -> caller index), off[257] bucket offsets and
+// bdw[257] dword offsets of the padded blocks.  scratch: 256*kRadixBlocks
+// uint32.
+void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
+                        uint32_t *scratch, hipStream_t s);
+
+// Padded copy of the strings in sorted order; writes slen, soff, str.
+// Reads bytes below min(nbytes_limit, offsets[n]); slots past str_cap dwords
+// are refused (err bit 4).
+void launch_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit, const uint32_t *perm,
+                   const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
+                   uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err, hipStream_t s);
+
+// Fingerprints (Section 3.2) of the sorted padded strings: fp_sorted[p],
+// fp_orig[perm[p]] (optional) and the filter keys.
+void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_t *slen, const uint32_t *perm,
+                         uint32_t n, const uint8_t *map, int variant, int bits, uint32_t *fp_sorted,
+                         uint32_t *fp_orig, void *keys, int key_kind, hipStream_t s);
+
+// Zero n uint32 words with a kernel (safe inside graph capture).
+void launch_zero(void *p, size_t n_u32, hipStream_t s);
+
+// ----------------------------------------------------------------- match
+void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
+                     uint32_t slab, uint32_t order, WorkList wl, hipStream_t s);
+// host-side twin used by the plain schedule
+uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
+                       uint32_t slab, uint32_t order, PairRec *pairs, uint32_t *n_pairs, uint64_t *examined);
+
+// Launch the fused filter -> LDS queue -> verify kernel.
+//   persistent: grid = persistent_blocks, items from the atomic counter;
+//   otherwise grid covers host_items items, one per wave.
+hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,
+                        uint32_t persistent_blocks, uint32_t host_items, hipStream_t s);
+
+// Exact distances of explicit (query, word) pairs given as caller indices;
+// qinv / dinv map caller index -> sorted position.
+hipError_t launch_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d, const uint32_t *dinv,
+                               const uint32_t *pairs, uint64_t n, int metric, uint32_t k, uint32_t *dist,
+                               hipStream_t s);
+
+// Inverse permutation: inv[perm[p]] = p.
+void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t s);
+
+// ----------------------------------------------------------------- sort
+// Stable LSD radix sort of n64 keys (count read from device) on bits
+// [lo_bit, hi_bit); ping-pongs between keys and tmp, the result ends in
+// *keys (data is copied back when the pass count is odd).  scratch:
+// 256*kRadixBlocks uint32.
+void launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
+                      uint32_t hi_bit, uint32_t *scratch, hipStream_t s);
+// Packed keys -> fpm_match triples (count read from device, clamped to cap).
+void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,
+                   int pairs_only, hipStream_t s);
+
+}  // namespace fpm

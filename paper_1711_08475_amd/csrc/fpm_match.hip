@@ -1,0 +1,573 @@
+// fpm_match.hip -- the matching hot path: fingerprint filter (Section 3.3,
+// Eq. 1), survivor compaction and exact verification, fused in one kernel.
+//
+// Work decomposition.  Queries and words are sorted by length, so a pair of
+// length buckets (query length m, word length L) is length-compatible when
+// L = m (Hamming; a Hamming distance between unequal lengths is infinite) or
+// |L - m| <= k (Levenshtein >= |L - m|).  Each compatible pair of buckets is
+// cut into work items: a tile of up to `qtile` queries of length m times a
+// slab of up to `slab` words of length L.  A work item belongs to one wave.
+//
+// Per work item, per 64 dictionary words (one per lane) and per 16 queries
+// (their filter keys are wave-uniform, so they sit in scalar registers):
+//   t   = popcount(kq ^ kw) - (2k + 1)   one v_xor, one v_bcnt with accumulator
+//   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
+// i.e. three vector instructions per (query, word) pair.  The lane's 16-bit
+// survivor mask is then appended to a per-wave queue in LDS (prefix sum of
+// the per-lane counts over the wave from five ballots); every time the queue
+// holds 64 entries the wave pops 64 and verifies them, one per lane, so the
+// verifier always runs on full waves.  Matches leave through one atomic per
+// wave and verification round.
+//
+// Verifiers (k-bounded, exact below k+1):
+//   Ham:   word-parallel mismatch count over 4-byte groups, exit above k;
+//   Lev 1: equal lengths -> Ham <= 1; lengths differing by one -> the shorter
+//          string s and longer t are one deletion apart iff the last
+//          position where s[j] != t[j+1] lies before the first position where
+//          s[j] != t[j]; both positions come from XORs of 4-byte groups
+//          (t shifted by one byte with v_alignbyte) and ctz / clz;
+//   Lev k>=2: the 2k+1 diagonal band of the edit-distance table (Ukkonen's
+//          cut-off, as the paper's 2k+1 strip), two band rows in registers.
+#include "fpm_internal.hpp"
+
+namespace fpm {
+
+namespace {
+
+constexpr int kWaves = 4;                 // waves per block, each independent
+constexpr int kChunk = 16;                // queries per filter pass = survivor-mask bits
+constexpr int kQueueCap = 64 * kChunk + 64;
+
+// -------------------------------------------------------------- filters
+// test() returns a value whose sign bit is set iff F_D <= 2k; `neg` holds
+// -(2k + 1).
+template <int KIND>
+struct Filter;
+
+template <>
+struct Filter<kPop32> {
+    using Key = uint32_t;
+    static __device__ __forceinline__ uint32_t test(Key q, Key w, uint32_t neg)
+    {
+        return (uint32_t)__builtin_popcount(q ^ w) + neg;
+    }
+};
+
+template <>
+struct Filter<kPop64> {
+    using Key = uint64_t;
+    static __device__ __forceinline__ uint32_t test(Key q, Key w, uint32_t neg)
+    {
+        const uint64_t x = q ^ w;
+        return (uint32_t)__builtin_popcount((uint32_t)x) + (uint32_t)__builtin_popcount((uint32_t)(x >> 32)) + neg;
+    }
+};
+
+// position fingerprints: count 3-bit fields that differ (a field differs
+// iff the OR of its three XOR bits is set, gathered at the field's low bit)
+// plus the differing occurrence bits.
+template <>
+struct Filter<kPos16> {
+    using Key = uint32_t;
+    static __device__ __forceinline__ uint32_t test(Key q, Key w, uint32_t neg)
+    {
+        const uint32_t x = q ^ w;
+        const uint32_t y = x | (x >> 1) | (x >> 2);
+        return (uint32_t)__builtin_popcount((y & 0x1249u) | (x & 0x8000u)) + neg;
+    }
+};
+
+template <>
+struct Filter<kPos32> {
+    using Key = uint32_t;
+    static __device__ __forceinline__ uint32_t test(Key q, Key w, uint32_t neg)
+    {
+        const uint32_t x = q ^ w;
+        const uint32_t y = x | (x >> 1) | (x >> 2);
+        return (uint32_t)__builtin_popcount((y & 0x09249249u) | (x & 0xC0000000u)) + neg;
+    }
+};
+
+template <>
+struct Filter<kAll> {
+    using Key = uint32_t;
+    static __device__ __forceinline__ uint32_t test(Key, Key, uint32_t) { return 0x80000000u; }
+};
+
+// ------------------------------------------------------------ verifiers
+
+// number of nonzero bytes of x
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
+{
+    return (uint32_t)__builtin_popcount((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+{
+    if (m != n)
+        return K + 1;
+    const uint32_t nw = (m + 3) >> 2;
+    uint32_t d = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+        d += nz_bytes(a[i] ^ b[i]);
+        if (d > (uint32_t)K)
+            return K + 1;
+    }
+    return d;
+}
+
+__device__ __forceinline__ uint32_t verify_lev1(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+{
+    if (m == n)
+        return verify_ham<1>(a, m, b, n);
+    if (m > n) {
+        const uint32_t *t = a;
+        a = b;
+        b = t;
+        const uint32_t u = m;
+        m = n;
+        n = u;
+    }
+    if (n - m != 1)
+        return 2;
+    // a: shorter (m), b: longer (n = m + 1), both zero padded to whole dwords
+    const uint32_t na = (m + 3) >> 2, nb = (n + 3) >> 2;
+    uint32_t first_a = m;  // first j < m with a[j] != b[j] (clamped to m)
+    int last_b = -1;       // last j with a[j] != b[j+1]
+    for (uint32_t i = 0; i < na; ++i) {
+        const uint32_t ai = a[i], bi = b[i];
+        const uint32_t bn = (i + 1 < nb) ? b[i + 1] : 0u;
+        const uint32_t A = ai ^ bi;
+        const uint32_t B = ai ^ __builtin_amdgcn_alignbyte(bn, bi, 1);
+        if (first_a == m && A != 0u)
+            first_a = min(4 * i + ((uint32_t)__builtin_ctz(A) >> 3), m);
+        if (B != 0u)
+            last_b = (int)(4 * i + ((31u - (uint32_t)__builtin_clz(B)) >> 3));
+        if (last_b >= (int)first_a)
+            return 2;
+    }
+    return 1;
+}
+
+__device__ __forceinline__ uint32_t byte_at(const uint32_t *s, uint32_t j)
+{
+    return (s[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+}
+
+// Banded edit distance, band |j - i| <= K, values saturated at K + 1.
+// Row i keeps cells j = i - K .. i + K in cur[0..2K].
+template <int K>
+__device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+{
+    const int gap = (int)n - (int)m;
+    if (gap > K || gap < -K)
+        return K + 1;
+    constexpr uint32_t INF = K + 1;
+    constexpr int W = 2 * K + 1;
+    uint32_t prev[W], cur[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        const int j = t - K;
+        prev[t] = (j >= 0 && j <= (int)n) ? min((uint32_t)j, INF) : INF;
+    }
+    for (uint32_t i = 1; i <= m; ++i) {
+        const uint32_t ai = byte_at(a, i - 1);
+        uint32_t rowmin = INF;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const int j = (int)i + t - K;
+            uint32_t v;
+            if (j < 0 || j > (int)n) {
+                v = INF;
+            } else if (j == 0) {
+                v = min(i, INF);
+            } else {
+                const uint32_t diag = prev[t] + (ai != byte_at(b, (uint32_t)j - 1) ? 1u : 0u);
+                const uint32_t up = (t + 1 < W) ? prev[t + 1] + 1u : INF;
+                const uint32_t left = (t >= 1) ? cur[t - 1] + 1u : INF;
+                v = min(min(diag, up), min(left, INF));
+            }
+            cur[t] = v;
+            rowmin = min(rowmin, v);
+        }
+        if (rowmin > (uint32_t)K)
+            return K + 1;
+#pragma unroll
+        for (int t = 0; t < W; ++t)
+            prev[t] = cur[t];
+    }
+    return prev[gap + K];
+}
+
+template <int METRIC, int K>
+__device__ __forceinline__ uint32_t verify(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+{
+    if (METRIC == 0)
+        return verify_ham<K>(a, m, b, n);
+    if (K == 1)
+        return verify_lev1(a, m, b, n);
+    return verify_lev_band<K>(a, m, b, n);
+}
+
+// Wave-uniform, read-only data (work list, query keys) is read through the
+// constant address space so that it is fetched with scalar loads into SGPRs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)(p);
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ---------------------------------------------------------- work items
+
+struct Item {
+    uint32_t qs, qn;  // sorted query range
+    uint32_t ds, de;  // sorted dictionary range
+};
+
+__device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, uint32_t n_pairs)
+{
+    // last pair whose item_base <= item (uniform binary search)
+    const cptr<PairRec> pairs = as_const(a.wl.pairs);
+    uint32_t lo = 0, hi = n_pairs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pairs[mid].item_base <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t base = pairs[lo].item_base, qbase = pairs[lo].qbase, nq = pairs[lo].nq;
+    const uint32_t dbase = pairs[lo].dbase, nd = pairs[lo].nd, tiles_d = pairs[lo].tiles_d;
+    const uint32_t t = item - base;
+    const uint32_t tq = t / tiles_d, td = t - tq * tiles_d;
+    Item it;
+    it.qs = qbase + tq * a.qtile;
+    it.qn = min(a.qtile, qbase + nq - it.qs);
+    it.ds = dbase + td * a.slab;
+    it.de = min(it.ds + a.slab, dbase + nd);
+    return it;
+}
+
+// Pop `nact` (<= 64) entries from the wave queue, verify one per lane and
+// emit matches.
+template <int METRIC, int K>
+__device__ __forceinline__ void drain(const MatchArgs &a, const uint2 *queue, uint32_t &qlen, uint32_t nact,
+                                      uint32_t lane, uint64_t &cells)
+{
+    __builtin_amdgcn_wave_barrier();
+    const bool act = lane < nact;
+    const uint2 ent = act ? queue[qlen - nact + lane] : make_uint2(0u, 0u);
+    __builtin_amdgcn_wave_barrier();
+    qlen -= nact;
+    uint32_t d = K + 1;
+    if (act) {
+        const uint32_t m = a.q.len[ent.x], n = a.d.len[ent.y];
+        cells += (uint64_t)(2 * K + 1) * min(m, n);
+        d = a.survivors_only ? 0u : verify<METRIC, K>(a.q.str + a.q.soff[ent.x], m, a.d.str + a.d.soff[ent.y], n);
+    }
+    const bool ok = act && d <= (uint32_t)K;
+    const uint64_t mm = __ballot(ok);
+    if (mm) {
+        unsigned long long base = 0;
+        if (lane == (uint32_t)__builtin_ctzll(mm))
+            base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)__popcll(mm));
+        base = __shfl(base, (int)__builtin_ctzll(mm));
+        if (ok) {
+            const uint64_t idx = base + lanes_below(mm);
+            if (idx < a.out_cap)
+                a.out_keys[idx] = ((uint64_t)a.q.perm[ent.x] << (a.wbits + 2)) | ((uint64_t)a.d.perm[ent.y] << 2) | d;
+        }
+    }
+}
+
+template <int KIND, int METRIC, int K, bool PERSISTENT>
+__global__ void __launch_bounds__(256) k_match(MatchArgs a)
+{
+    using F = Filter<KIND>;
+    using Key = typename F::Key;
+    __shared__ uint2 queue_all[kWaves][kQueueCap];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint2 *queue = queue_all[wave];
+    const cptr<Key> qkeys = as_const((const Key *)a.q.key);
+    const Key *__restrict__ dkeys = (const Key *)a.d.key;
+    const uint32_t neg = 0u - (2u * K + 1u);
+    const uint32_t n_items = *as_const(a.wl.n_items);
+    const uint32_t n_pairs = *as_const(a.wl.n_pairs);
+    uint32_t qlen = 0;
+    uint64_t survivors = 0;
+    uint64_t cells = 0;
+
+    uint32_t item;
+    if (PERSISTENT) {
+        uint32_t v = 0;
+        if (lane == 0)
+            v = atomicAdd(a.wl.counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(v);
+    } else {
+        item = blockIdx.x * kWaves + wave;
+    }
+    while (item < n_items) {
+        const Item it = decode_item(a, item, n_pairs);
+        for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            const bool valid = e < it.de;
+            const Key wk = valid ? dkeys[e] : Key(0);
+            for (uint32_t j0 = 0; j0 < it.qn; j0 += kChunk) {
+                const uint32_t nqc = min((uint32_t)kChunk, it.qn - j0);
+                const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry kChunk padding entries
+                uint32_t msk = 0;
+#pragma unroll
+                for (int t = 0; t < kChunk; ++t)
+                    msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
+                // bit (kChunk - 1 - t) <-> query j0 + t; drop the padding queries
+                msk &= (0xFFFFu << (kChunk - nqc)) & 0xFFFFu;
+                if (!valid)
+                    msk = 0;
+                const uint32_t c = (uint32_t)__builtin_popcount(msk);
+                if (__ballot(c != 0)) {
+                    uint32_t pre = 0, tot = 0;
+#pragma unroll
+                    for (int b = 0; b < 5; ++b) {
+                        const uint64_t m = __ballot((c >> b) & 1u);
+                        pre += lanes_below(m) << b;
+                        tot += (uint32_t)__popcll(m) << b;
+                    }
+                    uint32_t pos = qlen + pre;
+                    const uint32_t qbase = it.qs + j0 + (kChunk - 1);
+                    while (msk) {
+                        const uint32_t bit = 31u - (uint32_t)__builtin_clz(msk);
+                        queue[pos++] = make_uint2(qbase - bit, e);
+                        msk &= ~(1u << bit);
+                    }
+                    qlen += tot;
+                    survivors += tot;
+                    while (qlen >= 64)
+                        drain<METRIC, K>(a, queue, qlen, 64, lane, cells);
+                }
+            }
+        }
+        if (!PERSISTENT)
+            break;
+        uint32_t v = 0;
+        if (lane == 0)
+            v = atomicAdd(a.wl.counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(v);
+    }
+    if (qlen)
+        drain<METRIC, K>(a, queue, qlen, qlen, lane, cells);
+    // per-wave counters
+    for (int off = 32; off >= 1; off >>= 1)
+        cells += __shfl_xor(cells, off);
+    if (lane == 0) {
+        if (survivors)
+            atomicAdd((unsigned long long *)a.ctr.survivors, (unsigned long long)survivors);
+        if (cells)
+            atomicAdd((unsigned long long *)a.ctr.verify_cells, (unsigned long long)cells);
+    }
+}
+
+// --------------------------------------------------------- work list
+
+// One block: thread t owns query length m (descending or ascending order)
+// and its up to 2k+1 compatible word lengths.
+__global__ void __launch_bounds__(256) k_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k,
+                                                  uint32_t qtile, uint32_t slab, uint32_t order, WorkList wl)
+{
+    __shared__ uint32_t s_pairs[256], s_items[256];
+    __shared__ unsigned long long s_exam[256];
+    const uint32_t t = threadIdx.x;
+    const int m = order == 0 ? 255 - (int)t : (int)t;
+    const uint32_t nq = qoff[m + 1] - qoff[m];
+    const int r = metric == 0 ? 0 : (int)k;
+    uint32_t np = 0, ni = 0;
+    unsigned long long ex = 0;
+    if (nq) {
+        for (int L = m - r; L <= m + r; ++L) {
+            if (L < 0 || L > 255)
+                continue;
+            const uint32_t nd = doff[L + 1] - doff[L];
+            if (!nd)
+                continue;
+            np++;
+            ni += ((nq + qtile - 1) / qtile) * ((nd + slab - 1) / slab);
+            ex += (unsigned long long)nq * nd;
+        }
+    }
+    s_pairs[t] = np;
+    s_items[t] = ni;
+    s_exam[t] = ex;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        const uint32_t a = t >= o ? s_pairs[t - o] : 0, b = t >= o ? s_items[t - o] : 0;
+        const unsigned long long c = t >= o ? s_exam[t - o] : 0;
+        __syncthreads();
+        s_pairs[t] += a;
+        s_items[t] += b;
+        s_exam[t] += c;
+        __syncthreads();
+    }
+    uint32_t pidx = s_pairs[t] - np, ibase = s_items[t] - ni;
+    if (nq) {
+        for (int L = m - r; L <= m + r; ++L) {
+            if (L < 0 || L > 255)
+                continue;
+            const uint32_t nd = doff[L + 1] - doff[L];
+            if (!nd)
+                continue;
+            PairRec P;
+            P.item_base = ibase;
+            P.qbase = qoff[m];
+            P.nq = nq;
+            P.dbase = doff[L];
+            P.nd = nd;
+            P.tiles_d = (nd + slab - 1) / slab;
+            P.qlen = (uint32_t)m;
+            P.dlen = (uint32_t)L;
+            wl.pairs[pidx++] = P;
+            ibase += ((nq + qtile - 1) / qtile) * P.tiles_d;
+        }
+    }
+    if (t == 255) {
+        *wl.n_pairs = s_pairs[255];
+        *wl.n_items = s_items[255];
+        *wl.examined = s_exam[255];
+        *wl.counter = 0;
+    }
+}
+
+template <int METRIC, int K>
+__global__ void k_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d, const uint32_t *dinv,
+                               const uint32_t *pairs, uint64_t n, uint32_t *dist)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t qi = qinv[pairs[2 * i]], wi = dinv[pairs[2 * i + 1]];
+    dist[i] = verify<METRIC, K>(q.str + q.soff[qi], q.len[qi], d.str + d.soff[wi], d.len[wi]);
+}
+
+template <int KIND, int METRIC, int K>
+hipError_t launch_kmk(const MatchArgs &a, bool persistent, uint32_t pblocks, uint32_t host_items, hipStream_t s)
+{
+    if (persistent) {
+        hipLaunchKernelGGL((k_match<KIND, METRIC, K, true>), dim3(pblocks), dim3(256), 0, s, a);
+    } else {
+        if (host_items == 0)
+            return hipSuccess;
+        hipLaunchKernelGGL((k_match<KIND, METRIC, K, false>), dim3((host_items + kWaves - 1) / kWaves), dim3(256), 0,
+                           s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persistent, uint32_t pblocks,
+                       uint32_t host_items, hipStream_t s)
+{
+    if (metric == 0) {
+        if (k == 1)
+            return launch_kmk<KIND, 0, 1>(a, persistent, pblocks, host_items, s);
+        return launch_kmk<KIND, 0, 2>(a, persistent, pblocks, host_items, s);
+    }
+    if (k == 1)
+        return launch_kmk<KIND, 1, 1>(a, persistent, pblocks, host_items, s);
+    return launch_kmk<KIND, 1, 2>(a, persistent, pblocks, host_items, s);
+}
+
+}  // namespace
+
+uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
+                       uint32_t slab, uint32_t order, PairRec *pairs, uint32_t *n_pairs, uint64_t *examined)
+{
+    const int r = metric == 0 ? 0 : (int)k;
+    uint32_t np = 0, items = 0;
+    uint64_t ex = 0;
+    for (int t = 0; t < 256; ++t) {
+        const int m = order == 0 ? 255 - t : t;
+        const uint32_t nq = qoff[m + 1] - qoff[m];
+        if (!nq)
+            continue;
+        for (int L = m - r; L <= m + r; ++L) {
+            if (L < 0 || L > 255)
+                continue;
+            const uint32_t nd = doff[L + 1] - doff[L];
+            if (!nd)
+                continue;
+            PairRec &P = pairs[np++];
+            P.item_base = items;
+            P.qbase = qoff[m];
+            P.nq = nq;
+            P.dbase = doff[L];
+            P.nd = nd;
+            P.tiles_d = (nd + slab - 1) / slab;
+            P.qlen = (uint32_t)m;
+            P.dlen = (uint32_t)L;
+            items += ((nq + qtile - 1) / qtile) * P.tiles_d;
+            ex += (uint64_t)nq * nd;
+        }
+    }
+    *n_pairs = np;
+    *examined = ex;
+    return items;
+}
+
+void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
+                     uint32_t slab, uint32_t order, WorkList wl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(256), 0, s, qoff, doff, metric, k, qtile, slab, order, wl);
+}
+
+hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,
+                        uint32_t persistent_blocks, uint32_t host_items, hipStream_t s)
+{
+    switch (key_kind) {
+    case kPop32:
+        return launch_kind<kPop32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kPop64:
+        return launch_kind<kPop64>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kPos16:
+        if (metric != 0)
+            return hipErrorInvalidValue;
+        return k == 1 ? launch_kmk<kPos16, 0, 1>(a, persistent, persistent_blocks, host_items, s)
+                      : launch_kmk<kPos16, 0, 2>(a, persistent, persistent_blocks, host_items, s);
+    case kPos32:
+        if (metric != 0)
+            return hipErrorInvalidValue;
+        return k == 1 ? launch_kmk<kPos32, 0, 1>(a, persistent, persistent_blocks, host_items, s)
+                      : launch_kmk<kPos32, 0, 2>(a, persistent, persistent_blocks, host_items, s);
+    default:
+        return launch_kind<kAll>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    }
+}
+
+hipError_t launch_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d, const uint32_t *dinv,
+                               const uint32_t *pairs, uint64_t n, int metric, uint32_t k, uint32_t *dist,
+                               hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const dim3 g((uint32_t)((n + 255) / 256)), b(256);
+    if (metric == 0) {
+        if (k == 1)
+            hipLaunchKernelGGL((k_verify_pairs<0, 1>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+        else
+            hipLaunchKernelGGL((k_verify_pairs<0, 2>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+    } else {
+        if (k == 1)
+            hipLaunchKernelGGL((k_verify_pairs<1, 1>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+        else
+            hipLaunchKernelGGL((k_verify_pairs<1, 2>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fpm

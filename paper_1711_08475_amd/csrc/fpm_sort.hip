@@ -1,0 +1,216 @@
+// fpm_sort.hip -- stable LSD radix sort passes (8-bit digits) used for the
+// length bucketing of dictionaries and query batches and for the final
+// (query, word) ordering of the match list.
+//
+// One pass = three launches:
+//   hist:    kRadixBlocks blocks each count the digits of a contiguous range;
+//   scan:    one block turns the digit-major table [256][kRadixBlocks] into
+//            exclusive offsets, so block b's first item of digit d goes to
+//            offs[d][b];
+//   scatter: each block walks its range in order, one wave, 64 items at a
+//            time; lanes with equal digits are found with 8 ballots, so the
+//            rank of a lane among equal digits is the popcount of its peers
+//            below it -- the pass is stable.
+// The item count may live in device memory (match list), so every kernel
+// splits [0, n) into kRadixBlocks ranges at run time.
+#include "fpm_internal.hpp"
+
+namespace fpm {
+
+namespace {
+
+__device__ __forceinline__ uint64_t range_n(const uint64_t *dcount, uint64_t hcount, uint64_t cap)
+{
+    if (!dcount)
+        return hcount;
+    uint64_t n = *dcount;
+    return n < cap ? n : cap;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_t *dcount, uint64_t hcount,
+                                                    uint64_t cap, uint32_t shift, uint32_t *hist)
+{
+    __shared__ uint32_t h[256];
+    const uint32_t b = blockIdx.x;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t n = range_n(dcount, hcount, cap);
+    const uint64_t lo = n * b / kRadixBlocks, hi = n * (b + 1) / kRadixBlocks;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        uint32_t d = (uint32_t)(keys[i] >> shift) & 0xFFu;
+        atomicAdd(&h[d], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
+}
+
+// Exclusive scan of n entries in place, one block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v, uint32_t n)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = t * per, hi = min(n, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+        s += v[i];
+    part[t] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint32_t x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        uint32_t x = v[i];
+        v[i] = run;
+        run += x;
+    }
+}
+
+// One wave per block.  vals_in == nullptr means value = item index.
+template <typename K>
+__global__ void __launch_bounds__(64) k_radix_scatter(const K *keys_in, const uint32_t *vals_in, K *keys_out,
+                                                      uint32_t *vals_out, const uint64_t *dcount, uint64_t hcount,
+                                                      uint64_t cap, uint32_t shift, const uint32_t *offs)
+{
+    __shared__ uint32_t running[256];
+    const uint32_t b = blockIdx.x, lane = threadIdx.x;
+    for (uint32_t d = lane; d < 256; d += 64)
+        running[d] = offs[d * kRadixBlocks + b];
+    __syncthreads();
+    const uint64_t n = range_n(dcount, hcount, cap);
+    const uint64_t lo = n * b / kRadixBlocks, hi = n * (b + 1) / kRadixBlocks;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint64_t base = lo; base < hi; base += 64) {
+        const uint64_t i = base + lane;
+        const bool active = i < hi;
+        K key = active ? keys_in[i] : K(0);
+        uint32_t val = 0;
+        if (active)
+            val = vals_in ? vals_in[i] : (uint32_t)i;
+        const uint32_t digit = (uint32_t)(key >> shift) & 0xFFu;
+        uint64_t peers = __ballot(active);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (digit >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        uint32_t start = running[digit];
+        __builtin_amdgcn_wave_barrier();
+        if (active) {
+            const uint32_t rank = (uint32_t)__popcll(peers & below);
+            const uint32_t pos = start + rank;
+            if (keys_out)
+                keys_out[pos] = key;
+            if (vals_out)
+                vals_out[pos] = val;
+            if (rank == 0)
+                running[digit] = start + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+    }
+}
+
+// Bucket tables from the scanned digit table of a length pass:
+// off[L] = first sorted position of length L, bdw[L] = first dword of the
+// padded block of length L.
+__global__ void __launch_bounds__(256) k_bucket_tables(const uint32_t *offs, uint32_t n, uint32_t *off,
+                                                       uint32_t *bdw)
+{
+    __shared__ uint32_t part[256];
+    const uint32_t L = threadIdx.x;
+    const uint32_t start = offs[L * kRadixBlocks];
+    const uint32_t end = (L == 255) ? n : offs[(L + 1) * kRadixBlocks];
+    off[L] = start;
+    if (L == 255)
+        off[256] = n;
+    part[L] = (end - start) * slot_dwords(L);
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        uint32_t x = L >= o ? part[L - o] : 0;
+        __syncthreads();
+        part[L] += x;
+        __syncthreads();
+    }
+    bdw[L] = L ? part[L - 1] : 0;
+    if (L == 255)
+        bdw[256] = part[255];
+}
+
+__global__ void k_copy_u64(const uint64_t *src, uint64_t *dst, const uint64_t *dcount, uint64_t cap)
+{
+    const uint64_t n = range_n(dcount, 0, cap);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_unpack(const uint64_t *keys, const uint64_t *dcount, uint64_t cap, uint32_t wbits,
+                         uint32_t *triples, int pairs_only)
+{
+    const uint64_t n = range_n(dcount, 0, cap);
+    const uint64_t wmask = (wbits >= 64) ? ~0ull : ((1ull << wbits) - 1ull);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        const uint32_t d = (uint32_t)(k & 3ull);
+        const uint32_t w = (uint32_t)((k >> 2) & wmask);
+        const uint32_t q = (uint32_t)(k >> (2 + wbits));
+        if (pairs_only) {
+            triples[2 * i] = q;
+            triples[2 * i + 1] = w;
+        } else {
+            triples[3 * i] = q;
+            triples[3 * i + 1] = w;
+            triples[3 * i + 2] = d;
+        }
+    }
+}
+
+template <typename K>
+void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, const uint64_t *dcount, uint64_t hcount,
+                uint64_t cap, uint32_t shift, uint32_t *scratch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
+                       scratch);
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, scratch, 256u * kRadixBlocks);
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64), 0, s, kin, vin, kout, vout, dcount, hcount,
+                       cap, shift, scratch);
+}
+
+}  // namespace
+
+void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
+                        uint32_t *scratch, hipStream_t s)
+{
+    radix_pass<uint32_t>(len, nullptr, nullptr, perm, nullptr, n, n, 0, scratch, s);
+    hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
+}
+
+void launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
+                      uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
+{
+    uint64_t *a = keys, *b = tmp;
+    int passes = 0;
+    for (uint32_t shift = lo_bit; shift < hi_bit; shift += 8) {
+        radix_pass<uint64_t>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s);
+        uint64_t *t = a;
+        a = b;
+        b = t;
+        ++passes;
+    }
+    if (passes & 1)
+        hipLaunchKernelGGL(k_copy_u64, dim3(1024), dim3(256), 0, s, a, keys, count, cap);
+}
+
+void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,
+                   int pairs_only, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack, dim3(1024), dim3(256), 0, s, keys, count, cap, wbits, triples, pairs_only);
+}
+
+}  // namespace fpm

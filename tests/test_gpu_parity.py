@@ -1,0 +1,245 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element, on the
+same seeded inputs.  Every comparison is exact (integer work)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_08475_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+VARIANT_NAMES = {oracle.OCC: "occ", oracle.COUNT: "count", oracle.POS: "pos", oracle.OCCH: "occh"}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fpm(gpu):
+    from paper_1711_08475_amd import fpm as f
+
+    f.lib()
+    return f
+
+
+@pytest.fixture(scope="module")
+def small():
+    """10,000 English-like words (lengths 3-15) x 1,000 queries, half near-matches."""
+    return datagen.workload("english_10k_q1k")
+
+
+_oracle_cache = {}
+
+
+def oracle_match(key, d, q, metric, k):
+    if (key, metric, k) not in _oracle_cache:
+        _oracle_cache[(key, metric, k)] = oracle.match(d, q, metric, k)
+    return _oracle_cache[(key, metric, k)]
+
+
+# ---------------------------------------------------------------- symbols, fps
+
+@pytest.mark.parametrize("variant", [oracle.OCC, oracle.COUNT, oracle.POS, oracle.OCCH])
+@pytest.mark.parametrize("bits", [16, 32])
+@pytest.mark.parametrize("symset", [oracle.COMMON, oracle.RARE, oracle.MIXED])
+def test_symbol_map_and_fingerprints(fpm, small, variant, bits, symset):
+    d, q = small
+    say("fingerprints", VARIANT_NAMES[variant], bits, symset)
+    ref_map = oracle.select_symbols(oracle.histogram(d), variant, bits, symset)
+    assert np.array_equal(fpm.fpm_select_symbols(d, variant, bits, symset), ref_map)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, symset)
+    assert np.array_equal(fpm.fpm_get_map(ix), ref_map)
+    assert np.array_equal(fpm.fpm_get_fingerprints(ix), oracle.fingerprints(d, variant, bits, ref_map))
+    assert np.array_equal(fpm.fpm_fingerprints(ix, q), oracle.fingerprints(q, variant, bits, ref_map))
+
+
+def test_url_alphabet_fingerprints(fpm):
+    d, q = datagen.url_workload(3000, 100, 5)
+    for variant, bits in [(oracle.OCC, 32), (oracle.COUNT, 32), (oracle.POS, 32), (oracle.OCC, 16)]:
+        say("url fingerprints", VARIANT_NAMES[variant], bits)
+        ix = fpm.fpm_build_fingerprints(d, variant, bits, "mixed")
+        m = oracle.select_symbols(oracle.histogram(d), variant, bits, oracle.MIXED)
+        assert np.array_equal(fpm.fpm_get_fingerprints(ix), oracle.fingerprints(d, variant, bits, m))
+
+
+def test_custom_many_to_one_map(fpm, small):
+    d, q = small
+    rng = np.random.default_rng(4)
+    m = np.full(256, 255, dtype=np.uint8)
+    m[97:123] = rng.integers(0, 16, size=26)
+    m[ord("q")] = 255
+    say("custom map")
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=m)
+    assert np.array_equal(fpm.fpm_get_fingerprints(ix), oracle.fingerprints(d, oracle.OCC, 16, m))
+    got = fpm.fpm_match(ix, q, "lev", 1)
+    assert np.array_equal(got, oracle_match("small", d, q, oracle.LEV, 1))
+
+
+# ------------------------------------------------------------------ matching
+
+CASES = [
+    # (variant, bits, metric, k)
+    (oracle.OCC, 16, oracle.HAM, 1), (oracle.OCC, 16, oracle.LEV, 1), (oracle.OCC, 16, oracle.LEV, 2),
+    (oracle.OCC, 32, oracle.LEV, 1), (oracle.OCC, 32, oracle.HAM, 2),
+    (oracle.COUNT, 16, oracle.LEV, 1), (oracle.COUNT, 16, oracle.HAM, 1), (oracle.COUNT, 32, oracle.LEV, 1),
+    (oracle.COUNT, 32, oracle.LEV, 2),
+    (oracle.POS, 16, oracle.HAM, 1), (oracle.POS, 32, oracle.HAM, 1), (oracle.POS, 16, oracle.HAM, 2),
+    (oracle.OCCH, 16, oracle.HAM, 1), (oracle.OCCH, 32, oracle.HAM, 2),
+]
+
+
+@pytest.mark.parametrize("variant,bits,metric,k", CASES)
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_match_equals_oracle(fpm, small, variant, bits, metric, k, schedule):
+    d, q = small
+    say("match", VARIANT_NAMES[variant], bits, "ham" if metric == 0 else "lev", k, "schedule", schedule)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
+    got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule), with_stats=True)
+    ref = oracle_match("small", d, q, metric, k)
+    assert np.array_equal(got, ref)
+    # filter counters against the oracle's F_D counts
+    m = fpm.fpm_get_map(ix)
+    ex, surv, _ = oracle.filter_stats(d, q, variant, bits, m, metric, k)
+    assert st["pairs_examined"] == ex
+    assert st["survivors"] == surv
+    assert st["matches"] == ref.shape[0]
+    assert st["pairs_logical"] == (d[1].size - 1) * (q[1].size - 1)
+
+
+@pytest.mark.parametrize("metric,k", [(oracle.HAM, 1), (oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 2)])
+def test_bruteforce_equals_oracle(fpm, small, metric, k):
+    d, q = small
+    say("brute force", metric, k)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=fpm.FPM_SCHED_BRUTE), with_stats=True)
+    assert np.array_equal(got, oracle_match("small", d, q, metric, k))
+    assert st["survivors"] == st["pairs_examined"]
+
+
+@pytest.mark.parametrize("variant,bits,metric,k", [(oracle.OCC, 16, oracle.LEV, 1), (oracle.COUNT, 32, oracle.LEV, 2),
+                                                   (oracle.POS, 16, oracle.HAM, 1)])
+def test_filter_survivor_set(fpm, small, variant, bits, metric, k):
+    """The set of pairs the filter keeps equals {length-compatible pairs with
+    F_D <= 2k} computed from the oracle's fingerprints and F_D."""
+    d, q = small
+    q = datagen.take_csr(q, np.arange(200))
+    say("survivors", VARIANT_NAMES[variant], bits, metric, k)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
+    got = fpm.fpm_filter_pairs(ix, q, metric, k)
+    mp = fpm.fpm_get_map(ix)
+    fq, fw = oracle.fingerprints(q, variant, bits, mp), oracle.fingerprints(d, variant, bits, mp)
+    lq, lw = datagen.csr_lengths(q), datagen.csr_lengths(d)
+    rows = []
+    for i in range(lq.size):
+        gap = np.abs(lw - lq[i])
+        cand = np.nonzero(gap == 0 if metric == oracle.HAM else gap <= k)[0]
+        f = oracle.fd(np.full(cand.size, fq[i], dtype=np.uint32), fw[cand], variant, bits)
+        keep = cand[f <= 2 * k]
+        rows.append(np.stack([np.full(keep.size, i), keep], axis=1))
+    ref = np.concatenate(rows).astype(np.uint32)
+    assert np.array_equal(got, ref)
+
+
+def test_verify_pairs(fpm, small):
+    d, q = small
+    rng = np.random.default_rng(8)
+    pairs = np.stack([rng.integers(0, q[1].size - 1, 5000), rng.integers(0, d[1].size - 1, 5000)], 1).astype(np.uint32)
+    ref_pairs = oracle_match("small", d, q, oracle.LEV, 2)[:, :2]
+    pairs = np.concatenate([pairs, ref_pairs])
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1), (oracle.HAM, 2)]:
+        say("verify pairs", metric, k)
+        got = fpm.fpm_verify_pairs(ix, q, pairs, metric, k)
+        ref = oracle.pair_dist(d, q, pairs, metric)
+        assert np.array_equal(got, np.minimum(ref, k + 1))
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_edge_cases(fpm):
+    words = [b"", b"a", b"ab", b"ba", b"abc", b"x" * 255, b"x" * 254 + b"y", b"x" * 253, b"", b"aaaa", b"aaaa"]
+    queries = [b"", b"a", b"b", b"abc", b"x" * 255, b"x" * 254, b"aaaa", b"aaab", b"zzzzzzzz"]
+    d, q = datagen.to_csr(words), datagen.to_csr(queries)
+    for variant, bits, metric, k in [(oracle.OCC, 16, oracle.LEV, 1), (oracle.OCC, 32, oracle.LEV, 2),
+                                     (oracle.COUNT, 16, oracle.HAM, 2), (oracle.POS, 32, oracle.HAM, 1)]:
+        for sched in (0, 1, 2):
+            say("edge", VARIANT_NAMES[variant], bits, metric, k, sched)
+            ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
+            got = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched))
+            assert np.array_equal(got, oracle.match(d, q, metric, k))
+
+
+def test_empty_inputs(fpm):
+    d = datagen.to_csr([b"abc", b"abd"])
+    e = datagen.to_csr([])
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    say("empty queries")
+    assert fpm.fpm_match(ix, e, "lev", 1).shape == (0, 3)
+    say("empty dictionary")
+    ix0 = fpm.fpm_build_fingerprints(e, "occ", 16, "common")
+    assert fpm.fpm_match(ix0, d, "lev", 1).shape == (0, 3)
+
+
+def test_everything_survives_and_ragged_buckets(fpm):
+    """A map with no symbols makes every fingerprint 0, so every examined pair
+    survives: the queues fill on every pass.  Bucket sizes are not multiples
+    of 64 or of the tile sizes."""
+    rng = np.random.default_rng(12)
+    words = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(3001)]
+    queries = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(77)]
+    d, q = datagen.to_csr(words), datagen.to_csr(queries)
+    none = np.full(256, 255, dtype=np.uint8)
+    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
+        ref = oracle.match(d, q, metric, k)
+        for sched, qt, slab in [(0, 16, 64), (1, 32, 128), (1, 1024, 1 << 20), (0, 64, 16384)]:
+            say("all survive", metric, k, sched, qt, slab)
+            ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=none)
+            got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched, queries_per_item=qt, slab=slab),
+                                    with_stats=True)
+            assert np.array_equal(got, ref)
+            assert st["survivors"] == st["pairs_examined"]
+
+
+def test_match_buffer_growth(fpm, small):
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    for sched in (0, 1):
+        say("tiny match buffer", sched)
+        got = fpm.fpm_match(ix, q, "lev", 2, fpm.options(schedule=sched, match_capacity=7))
+        assert np.array_equal(got, oracle_match("small", d, q, oracle.LEV, 2))
+
+
+def test_errors(fpm, small):
+    d, q = small
+    ix_pos = fpm.fpm_build_fingerprints(d, "pos", 16, "common")
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix_pos, q, "lev", 1)
+    assert e.value.status == fpm.FPM_EUNSUPPORTED
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, q, "lev", 3)
+    assert e.value.status == fpm.FPM_EUNSUPPORTED
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_build_fingerprints(d, "occ", 8, "common")
+    assert e.value.status == fpm.FPM_EINVAL
+    bad = np.full(256, 255, dtype=np.uint8)
+    bad[97] = 8
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_build_fingerprints(d, "count", 16, custom_map=bad)
+    assert e.value.status == fpm.FPM_EINVAL
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, datagen.to_csr([b"a" * 256]), "lev", 1)
+    assert e.value.status == fpm.FPM_EINVAL
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, q, "lev", 1, fpm.options(queries_per_item=24))
+    assert e.value.status == fpm.FPM_EINVAL
+
+
+def test_deterministic_repeats(fpm, small):
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    say("repeats")
+    first = fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1))
+    for _ in range(3):
+        assert np.array_equal(fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1)), first)

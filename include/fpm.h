@@ -102,12 +102,15 @@ typedef struct {
 typedef struct {
     uint32_t schedule;         /* fpm_schedule */
     uint32_t queries_per_item; /* queries per work item, multiple of 16, <= 1024 (default 64) */
-    uint32_t slab;             /* dictionary words per work item, multiple of 64 (default 16384) */
+    uint32_t slab;             /* dictionary words per work item, multiple of 64, <= 4M (default 4096) */
     uint32_t bucket_order;     /* 0: longest query length first, 1: shortest first */
     uint32_t use_graph;        /* batched only: 1 = capture/replay a hipGraph (default 1), 2 = plain launches */
-    uint32_t waves_per_cu;     /* batched only: persistent waves per compute unit (default 16) */
+    uint32_t waves_per_cu;     /* batched only: persistent waves per compute unit (default 32) */
     uint32_t match_capacity;   /* initial device match buffer (entries; default 1 << 20); grows on overflow */
-    uint32_t reserved[9];
+    uint32_t time_kernel;      /* 1: bracket the match kernel of every run with HIP events (see
+                                  fpm_plan_kernel_ms); a batched graph is then split into a prep graph
+                                  and a post graph around a direct launch of the match kernel */
+    uint32_t reserved[8];
 } fpm_options;
 
 typedef struct fpm_index fpm_index;
@@ -207,6 +210,11 @@ fpm_status fpm_plan_run(fpm_plan *plan, const uint8_t *d_qbytes, const uint64_t 
  * may be NULL. */
 fpm_status fpm_plan_result(fpm_plan *plan, const fpm_hit **d_matches, uint64_t *n_out, fpm_stats *stats);
 
+/* Durations in ms of the match kernel of the last min(runs, max, 256) runs,
+ * oldest first, for a plan created with time_kernel = 1 (waits for the
+ * stream).  *n receives the count written to ms_out. */
+fpm_status fpm_plan_kernel_ms(fpm_plan *plan, float *ms_out, uint32_t max, uint32_t *n);
+
 /* Copy up to `max` matches of the last run into dst (host or device memory,
  * hipMemcpyDefault), synchronously; *n_copied receives the number copied. */
 fpm_status fpm_plan_copy_matches(fpm_plan *plan, fpm_hit *dst, uint64_t max, uint64_t *n_copied);
@@ -214,8 +222,8 @@ fpm_status fpm_plan_copy_matches(fpm_plan *plan, fpm_hit *dst, uint64_t max, uin
 void fpm_plan_destroy(fpm_plan *plan);
 
 /* Autotuner for the batched schedule: times every combination of
- * queries_per_item in {16, 32, 64, 128, 256}, slab in {4096, 8192, 16384,
- * 32768, 65536} and both bucket orders on the given device queries, and
+ * queries_per_item in {16, 32, 64, 128, 256}, slab in {512, 1024, 2048,
+ * 4096, 8192, 16384} and both bucket orders on the given device queries, and
  * writes the fastest into *best (its schedule = FPM_SCHED_BATCHED).
  * `timings_out` (nullable) receives up to `max_timings` rows of
  * (queries_per_item, slab, bucket_order, ms) as floats. */

@@ -23,6 +23,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
+constexpr uint32_t kRing = 256;  // kernel-timing event pairs per plan
+
 fpm_status fail(fpm_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -111,9 +113,9 @@ struct StrSet {
         if ((e = dalloc(&len, max_n)) || (e = dalloc(&perm, max_n)) || (e = dalloc(&soff, max_n)) ||
             (e = dalloc(&slen, max_n)) || (e = dalloc(&off, 257)) || (e = dalloc(&bdw, 257)))
             return e;
-        // padded strings: sum over strings of max(1, ceil(L/4)) dwords, which is
-        // at most bytes/4 + n and at most 64 per string
-        str_cap = std::min<uint64_t>(max_bytes / 4 + (uint64_t)max_n, (uint64_t)max_n * 64) + 16;
+        // padded strings: a slot holds at most L/4 + 3 dwords and at most 64,
+        // each of the 256 length blocks adds at most 3 dwords of alignment
+        str_cap = std::min<uint64_t>(max_bytes / 4 + 3ull * max_n, (uint64_t)max_n * 64) + 1024 + 16;
         if ((e = dalloc(&str, str_cap)))
             return e;
         // keys carry one filter chunk of padding (read, never used)
@@ -207,13 +209,29 @@ struct fpm_plan {
     uint32_t host_items = 0;
     uint64_t host_examined = 0;
 
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gall = nullptr, gpre = nullptr, gpost = nullptr;
+    bool g_valid = false;
     const uint8_t *g_bytes = nullptr;
     const uint64_t *g_offsets = nullptr;
     uint32_t g_nq = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t kev[2][kRing] = {};
+    uint64_t runs = 0;
     std::vector<PairRec> h_pairs;
+    uint32_t h_hdr[2] = {0, 0};  // host source of an async copy: lives in the plan
+
+    WorkList worklist() { return WorkList{pairs, &ctr->n_pairs, &ctr->n_items, &ctr->counter, &ctr->examined}; }
+
+    void drop_graphs()
+    {
+        for (hipGraphExec_t *g : {&gall, &gpre, &gpost}) {
+            if (*g)
+                (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
+        g_valid = false;
+    }
 
     fpm_status alloc_output(uint64_t cap_entries)
     {
@@ -224,10 +242,7 @@ struct fpm_plan {
         HIPCHK(dalloc(&keys, cap));
         HIPCHK(dalloc(&tmp, cap));
         HIPCHK(dalloc(&triples, cap * 3));
-        if (gexec) {
-            (void)hipGraphExecDestroy(gexec);
-            gexec = nullptr;
-        }
+        drop_graphs();
         return FPM_OK;
     }
 };
@@ -439,8 +454,11 @@ static void plan_free(fpm_plan *p)
 {
     if (!p)
         return;
-    if (p->gexec)
-        (void)hipGraphExecDestroy(p->gexec);
+    p->drop_graphs();
+    for (int i = 0; i < 2; ++i)
+        for (uint32_t j = 0; j < kRing; ++j)
+            if (p->kev[i][j])
+                (void)hipEventDestroy(p->kev[i][j]);
     p->q.release();
     dfree(p->scratch);
     dfree(p->pairs);
@@ -480,21 +498,23 @@ static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
     if (!o->queries_per_item)
         o->queries_per_item = 64;
     if (!o->slab)
-        o->slab = 16384;
+        o->slab = 4096;
     if (!o->use_graph)
         o->use_graph = 1;
     if (!o->waves_per_cu)
-        o->waves_per_cu = 16;
+        o->waves_per_cu = 32;
     if (!o->match_capacity)
         o->match_capacity = 1u << 20;
     if (o->queries_per_item % 16 || o->queries_per_item > 1024)
         return fail(FPM_EINVAL, "queries_per_item must be a multiple of 16 up to 1024");
-    if (o->slab % 64 || o->slab < 64 || o->slab > (1u << 24))
-        return fail(FPM_EINVAL, "slab must be a multiple of 64 in 64..16M");
+    if (o->slab % 64 || o->slab < 64 || o->slab > (1u << 22))
+        return fail(FPM_EINVAL, "slab must be a multiple of 64 in 64..4M");
     if (o->bucket_order > 1)
         return fail(FPM_EINVAL, "bucket_order must be 0 or 1");
     if (o->waves_per_cu > 64)
         return fail(FPM_EINVAL, "waves_per_cu must be <= 64");
+    if (o->time_kernel > 1)
+        return fail(FPM_EINVAL, "time_kernel must be 0 or 1");
     return FPM_OK;
 }
 
@@ -548,6 +568,14 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         plan_free(p);
         return st;
     }
+    if (p->opt.time_kernel == 1) {
+        for (int i = 0; i < 2; ++i)
+            for (uint32_t j = 0; j < kRing; ++j)
+                if ((e = hipEventCreate(&p->kev[i][j]))) {
+                    plan_free(p);
+                    return hip_fail(e, "kernel timing events");
+                }
+    }
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess)
@@ -565,9 +593,11 @@ fpm_status fpm_plan_create(const fpm_index *ix, uint32_t max_queries, uint64_t m
     return plan_create(ix, max_queries, max_query_bytes, metric, k, opt, hip_stream, false, out);
 }
 
-// Everything of one match that runs on the device.  With `plain` the
-// host reads the query bucket table in the middle (one synchronisation).
-static fpm_status plan_enqueue(fpm_plan *p, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t nq,
+// The device work of one match in three parts: prep (query staging,
+// fingerprints, work list), the match kernel, post (sort, unpack).  With
+// `plain` the host reads the query bucket table during prep (one
+// synchronisation).
+static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t nq,
                                bool plain)
 {
     const fpm_index *ix = p->ix;
@@ -576,7 +606,6 @@ static fpm_status plan_enqueue(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     const bool fps = p->kind != kAll;
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
                  fps ? p->kind : kPop32, fps, &p->ctr->err, p->scratch, s);
-    WorkList wl{p->pairs, &p->ctr->n_pairs, &p->ctr->n_items, &p->ctr->counter, &p->ctr->examined};
     if (plain) {
         uint32_t h_qoff[257];
         HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));
@@ -584,23 +613,26 @@ static fpm_status plan_enqueue(fpm_plan *p, const uint8_t *d_qbytes, const uint6
         uint32_t np = 0;
         p->host_items = host_worklist(h_qoff, ix->h_off, p->metric, p->k, p->opt.queries_per_item, p->opt.slab,
                                       p->opt.bucket_order, p->h_pairs.data(), &np, &p->host_examined);
-        struct {
-            uint32_t n_pairs, n_items;
-        } hdr{np, p->host_items};
+        p->h_hdr[0] = np;
+        p->h_hdr[1] = p->host_items;
         if (np)
             HIPCHK(hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(PairRec) * np, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(&p->ctr->n_pairs, &hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(&p->ctr->n_pairs, p->h_hdr, sizeof(p->h_hdr), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(&p->ctr->examined, &p->host_examined, sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        // the copies read host stack memory: finish them before returning
-        HIPCHK(hipStreamSynchronize(s));
     } else {
         launch_worklist(p->q.off, ix->words.off, p->metric, p->k, p->opt.queries_per_item, p->opt.slab,
-                        p->opt.bucket_order, wl, s);
+                        p->opt.bucket_order, p->worklist(), s);
     }
+    return FPM_OK;
+}
+
+static fpm_status enqueue_kernel(fpm_plan *p, bool plain)
+{
+    const fpm_index *ix = p->ix;
     MatchArgs a;
     a.q = p->q.view();
     a.d = ix->words.view();
-    a.wl = wl;
+    a.wl = p->worklist();
     a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells};
     a.out_keys = p->keys;
     a.out_cap = p->cap;
@@ -608,12 +640,46 @@ static fpm_status plan_enqueue(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     a.slab = p->opt.slab;
     a.wbits = ix->wbits;
     a.survivors_only = p->survivors_only ? 1u : 0u;
-    hipError_t e = launch_match(a, p->kind, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks, p->host_items, s);
+    hipError_t e =
+        launch_match(a, p->kind, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks, p->host_items, p->stream);
     if (e)
         return hip_fail(e, "match kernel launch");
+    return FPM_OK;
+}
+
+static void enqueue_post(fpm_plan *p, uint32_t nq)
+{
+    const fpm_index *ix = p->ix;
     const uint32_t qbits = bits_for(std::max<uint32_t>(nq, 1));
-    launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, s);
-    launch_unpack(p->keys, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, s);
+    launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, p->stream);
+    launch_unpack(p->keys, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, p->stream);
+}
+
+static fpm_status capture(fpm_plan *p, hipGraphExec_t *out, int part, const uint8_t *b, const uint64_t *o,
+                          uint32_t nq)
+{
+    hipStream_t s = p->stream;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    fpm_status st = FPM_OK;
+    if (part & 1)
+        st = enqueue_prep(p, b, o, nq, false);
+    if (!st && (part & 2))
+        st = enqueue_kernel(p, false);
+    if (!st && (part & 4))
+        enqueue_post(p, nq);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e)
+        return hip_fail(e, "graph capture");
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e)
+        return hip_fail(e, "graph instantiate");
     return FPM_OK;
 }
 
@@ -622,39 +688,71 @@ static fpm_status plan_launch(fpm_plan *p, const uint8_t *d_qbytes, const uint64
     hipStream_t s = p->stream;
     const bool plain = p->opt.schedule != FPM_SCHED_BATCHED;
     const bool graph = !plain && p->opt.use_graph == 1;
+    const bool timed = p->opt.time_kernel == 1;
+    const uint32_t slot = (uint32_t)(p->runs % kRing);
     HIPCHK(hipEventRecord(p->ev0, s));
     if (graph) {
-        if (!p->gexec || p->g_bytes != d_qbytes || p->g_offsets != d_qoffsets || p->g_nq != nq) {
-            if (p->gexec) {
-                (void)hipGraphExecDestroy(p->gexec);
-                p->gexec = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            fpm_status st = plan_enqueue(p, d_qbytes, d_qoffsets, nq, false);
-            hipError_t e = hipStreamEndCapture(s, &g);
-            if (st) {
-                if (g)
-                    (void)hipGraphDestroy(g);
+        if (!p->g_valid || p->g_bytes != d_qbytes || p->g_offsets != d_qoffsets || p->g_nq != nq) {
+            p->drop_graphs();
+            fpm_status st = timed ? capture(p, &p->gpre, 1, d_qbytes, d_qoffsets, nq)
+                                  : capture(p, &p->gall, 7, d_qbytes, d_qoffsets, nq);
+            if (!st && timed)
+                st = capture(p, &p->gpost, 4, d_qbytes, d_qoffsets, nq);
+            if (st)
                 return st;
-            }
-            if (e)
-                return hip_fail(e, "graph capture");
-            e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e)
-                return hip_fail(e, "graph instantiate");
+            p->g_valid = true;
             p->g_bytes = d_qbytes;
             p->g_offsets = d_qoffsets;
             p->g_nq = nq;
         }
-        HIPCHK(hipGraphLaunch(p->gexec, s));
+        if (timed) {
+            HIPCHK(hipGraphLaunch(p->gpre, s));
+            HIPCHK(hipEventRecord(p->kev[0][slot], s));
+            fpm_status st = enqueue_kernel(p, false);
+            if (st)
+                return st;
+            HIPCHK(hipEventRecord(p->kev[1][slot], s));
+            HIPCHK(hipGraphLaunch(p->gpost, s));
+        } else {
+            HIPCHK(hipGraphLaunch(p->gall, s));
+        }
     } else {
-        fpm_status st = plan_enqueue(p, d_qbytes, d_qoffsets, nq, plain);
+        fpm_status st = enqueue_prep(p, d_qbytes, d_qoffsets, nq, plain);
         if (st)
             return st;
+        if (timed)
+            HIPCHK(hipEventRecord(p->kev[0][slot], s));
+        st = enqueue_kernel(p, plain);
+        if (st)
+            return st;
+        if (timed)
+            HIPCHK(hipEventRecord(p->kev[1][slot], s));
+        enqueue_post(p, nq);
     }
     HIPCHK(hipEventRecord(p->ev1, s));
+    if (timed)
+        p->runs++;
+    return FPM_OK;
+}
+
+fpm_status fpm_plan_kernel_ms(fpm_plan *p, float *ms_out, uint32_t max, uint32_t *n)
+{
+    g_last_error.clear();
+    if (!p || (max && !ms_out))
+        return fail(FPM_EINVAL, "null pointer");
+    if (p->opt.time_kernel != 1)
+        return fail(FPM_EINVAL, "plan was created without time_kernel");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const uint64_t avail = std::min<uint64_t>(p->runs, kRing);
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(avail, max);
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t slot = (uint32_t)((p->runs - cnt + i) % kRing);
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p->kev[0][slot], p->kev[1][slot]));
+        ms_out[i] = ms;
+    }
+    if (n)
+        *n = cnt;
     return FPM_OK;
 }
 
@@ -924,7 +1022,7 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
     if (!ix || !best)
         return fail(FPM_EINVAL, "null pointer");
     static const uint32_t qts[] = {16, 32, 64, 128, 256};
-    static const uint32_t slabs[] = {4096, 8192, 16384, 32768, 65536};
+    static const uint32_t slabs[] = {512, 1024, 2048, 4096, 8192, 16384};
     if (repeats == 0)
         repeats = 3;
     fpm_options base = *best;

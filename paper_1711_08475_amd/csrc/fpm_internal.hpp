@@ -4,8 +4,10 @@
 // Device layout of a string set (dictionary or query batch), all in HBM:
 //   * strings are stably sorted by length; strings of length L occupy the
 //     sorted positions [off[L], off[L+1]);
-//   * each string is copied into a zero-padded slot of sw(L) = max(1,
-//     ceil(L/4)) dwords; the slots of one length form one dense block;
+//   * each string is copied into a zero-padded slot of sw(L) dwords: 1 for
+//     L <= 4, 2 for L <= 8, else 4 * ceil(L / 16), so that a slot is read
+//     with one dword, one dwordx2 or dwordx4 loads; the slots of one length
+//     form one dense block whose base is 16-byte aligned;
 //     soff[p] is the dword offset of sorted string p, len[p] its length and
 //     perm[p] its position in the caller's list;
 //   * key[p] is the filter key of string p (see fpm_match.hip): the
@@ -23,7 +25,10 @@ constexpr int kBuckets = 256;        // lengths 0..255
 constexpr int kMaxPairs = 256 * 5;   // (query length, word length) pairs, |dL| <= 2
 constexpr int kRadixBlocks = 256;    // blocks of one stable radix pass
 
-__host__ __device__ inline uint32_t slot_dwords(uint32_t len) { return len == 0 ? 1u : (len + 3u) >> 2; }
+__host__ __device__ inline uint32_t slot_dwords(uint32_t len)
+{
+    return len <= 4 ? 1u : len <= 8 ? 2u : 4u * ((len + 15u) >> 4);
+}
 
 // Filter-key families.  Pop32: F_D = popc(kq ^ kw) on 32-bit keys (occ,
 // occ-halved, 16-bit count thermometer); Pop64: the same on 64-bit keys

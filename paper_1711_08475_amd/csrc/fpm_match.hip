@@ -17,7 +17,7 @@
 // the per-lane counts over the wave from five ballots); every time the queue
 // holds 64 entries the wave pops 64 and verifies them, one per lane, so the
 // verifier always runs on full waves.  Matches leave through one atomic per
-// wave and verification round.
+// flush of a per-wave LDS staging buffer.
 //
 // Verifiers (k-bounded, exact below k+1):
 //   Ham:   word-parallel mismatch count over 4-byte groups, exit above k;
@@ -36,7 +36,13 @@ namespace {
 
 constexpr int kWaves = 4;                 // waves per block, each independent
 constexpr int kChunk = 16;                // queries per filter pass = survivor-mask bits
-constexpr int kQueueCap = 64 * kChunk + 64;
+constexpr int kQueueCap = 64 * kChunk + 64;  // entries per wave: < 64 left + one full pass
+// Matches are staged per wave in LDS and leave through one atomic per flush;
+// a flush happens once more than kOutFlush are staged, so a drain (<= 64
+// new matches) always fits.  Queue + staging = 5120 bytes per wave, 20 KB
+// per block: eight blocks fill the 160 KB of LDS of a compute unit.
+constexpr int kOutCap = 96;
+constexpr int kOutFlush = kOutCap - 64;
 
 // -------------------------------------------------------------- filters
 // test() returns a value whose sign bit is set iff F_D <= 2k; `neg` holds
@@ -95,6 +101,30 @@ struct Filter<kAll> {
 };
 
 // ------------------------------------------------------------ verifiers
+// All verifiers see wave-uniform lengths (every entry of a drain comes from
+// one work item, i.e. one pair of length buckets), so loop trip counts and
+// branches on lengths are uniform; strings are read from their padded slots
+// 16 bytes at a time.
+
+// Dwords 4c..4c+3 of a string in a slot of sw dwords (1, 2 or a multiple of
+// 4, aligned to its size), zero beyond the slot.  sw and c are uniform.
+__device__ __forceinline__ uint4 chunk(const uint32_t *p, uint32_t sw, uint32_t c)
+{
+    if (sw >= 4)
+        return (4 * c < sw) ? *(const uint4 *)(p + 4 * c) : make_uint4(0u, 0u, 0u, 0u);
+    if (c)
+        return make_uint4(0u, 0u, 0u, 0u);
+    if (sw == 2) {
+        const uint2 v = *(const uint2 *)p;
+        return make_uint4(v.x, v.y, 0u, 0u);
+    }
+    return make_uint4(p[0], 0u, 0u, 0u);
+}
+
+__device__ __forceinline__ uint32_t dword_of(const uint4 &v, int t)
+{
+    return t == 0 ? v.x : t == 1 ? v.y : t == 2 ? v.z : v.w;
+}
 
 // number of nonzero bytes of x
 __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
@@ -102,63 +132,96 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
     return (uint32_t)__builtin_popcount((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
 }
 
+// Hamming distance of two strings of length m, capped at K + 1.
 template <int K>
-__device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+__device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, uint32_t sa, const uint32_t *b, uint32_t sb,
+                                               uint32_t m)
 {
-    if (m != n)
-        return K + 1;
-    const uint32_t nw = (m + 3) >> 2;
+    const uint32_t nch = (m + 15) >> 4;
     uint32_t d = 0;
-    for (uint32_t i = 0; i < nw; ++i) {
-        d += nz_bytes(a[i] ^ b[i]);
-        if (d > (uint32_t)K)
-            return K + 1;
+    for (uint32_t c = 0; c < nch; ++c) {
+        const uint4 A = chunk(a, sa, c), B = chunk(b, sb, c);
+        d += nz_bytes(A.x ^ B.x) + nz_bytes(A.y ^ B.y) + nz_bytes(A.z ^ B.z) + nz_bytes(A.w ^ B.w);
+        if (!__any(d <= (uint32_t)K))
+            break;
     }
-    return d;
+    return min(d, (uint32_t)K + 1);
 }
 
-__device__ __forceinline__ uint32_t verify_lev1(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+// Levenshtein distance <= 1 test.  Equal lengths: Hamming <= 1.  Lengths m
+// and m + 1: with a the shorter string and b the longer one, b becomes a by
+// deleting one symbol iff every position j with a[j] != b[j + 1] lies before
+// the first position with a[j] != b[j] (then delete b at that position).
+__device__ __forceinline__ uint32_t verify_lev1(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b,
+                                                uint32_t sb, uint32_t n)
 {
     if (m == n)
-        return verify_ham<1>(a, m, b, n);
+        return verify_ham<1>(a, sa, b, sb, m);
     if (m > n) {
         const uint32_t *t = a;
         a = b;
         b = t;
-        const uint32_t u = m;
+        uint32_t u = sa;
+        sa = sb;
+        sb = u;
+        u = m;
         m = n;
         n = u;
     }
     if (n - m != 1)
         return 2;
-    // a: shorter (m), b: longer (n = m + 1), both zero padded to whole dwords
-    const uint32_t na = (m + 3) >> 2, nb = (n + 3) >> 2;
-    uint32_t first_a = m;  // first j < m with a[j] != b[j] (clamped to m)
-    int last_b = -1;       // last j with a[j] != b[j+1]
-    for (uint32_t i = 0; i < na; ++i) {
-        const uint32_t ai = a[i], bi = b[i];
-        const uint32_t bn = (i + 1 < nb) ? b[i + 1] : 0u;
-        const uint32_t A = ai ^ bi;
-        const uint32_t B = ai ^ __builtin_amdgcn_alignbyte(bn, bi, 1);
-        if (first_a == m && A != 0u)
-            first_a = min(4 * i + ((uint32_t)__builtin_ctz(A) >> 3), m);
-        if (B != 0u)
-            last_b = (int)(4 * i + ((31u - (uint32_t)__builtin_clz(B)) >> 3));
-        if (last_b >= (int)first_a)
-            return 2;
+    const uint32_t nch = (m + 15) >> 4;
+    uint32_t first_a = m;  // first j with a[j] != b[j], clamped to m
+    int last_b = -1;       // last j with a[j] != b[j + 1]
+    uint4 B = chunk(b, sb, 0);
+    for (uint32_t c = 0; c < nch; ++c) {
+        const uint4 A = chunk(a, sa, c);
+        const uint4 Bn = chunk(b, sb, c + 1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t ai = dword_of(A, t), bi = dword_of(B, t);
+            const uint32_t bn = t < 3 ? dword_of(B, t + 1) : Bn.x;
+            const uint32_t xa = ai ^ bi;
+            const uint32_t xb = ai ^ __builtin_amdgcn_alignbyte(bn, bi, 1);
+            const uint32_t pos = 16 * c + 4 * t;
+            if (first_a == m && xa != 0u)
+                first_a = min(pos + ((uint32_t)__builtin_ctz(xa) >> 3), m);
+            if (xb != 0u)
+                last_b = (int)(pos + ((31u - (uint32_t)__builtin_clz(xb)) >> 3));
+        }
+        if (!__any(last_b < (int)first_a))
+            break;
+        B = Bn;
     }
-    return 1;
+    return last_b < (int)first_a ? 1u : 2u;
 }
 
-__device__ __forceinline__ uint32_t byte_at(const uint32_t *s, uint32_t j)
-{
-    return (s[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-}
+// Bytes of a padded string in order, one dword load per four bytes; indices
+// below zero or past the slot read as zero.  The read schedule depends only
+// on the (uniform) index.
+struct ByteStream {
+    const uint32_t *p;
+    uint32_t sw;
+    int idx;
+    uint32_t cur;
+    __device__ __forceinline__ uint32_t next()
+    {
+        const int i = idx++;
+        if (i < 0)
+            return 0u;
+        if ((i & 3) == 0)
+            cur = ((uint32_t)i >> 2) < sw ? p[i >> 2] : 0u;
+        return (cur >> (8 * (i & 3))) & 0xFFu;
+    }
+};
 
-// Banded edit distance, band |j - i| <= K, values saturated at K + 1.
-// Row i keeps cells j = i - K .. i + K in cur[0..2K].
+// Banded edit distance (Ukkonen's cut-off: only |j - i| <= K matters when
+// the distance is at most K), values saturated at K + 1.  Row i keeps cells
+// j = i - K .. i + K; `win` holds the symbols b[j - 1] those cells compare,
+// byte t for j = i + t - K.
 template <int K>
-__device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+__device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b,
+                                                    uint32_t sb, uint32_t n)
 {
     const int gap = (int)n - (int)m;
     if (gap > K || gap < -K)
@@ -171,8 +234,14 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
         const int j = t - K;
         prev[t] = (j >= 0 && j <= (int)n) ? min((uint32_t)j, INF) : INF;
     }
+    ByteStream as{a, sa, 0, 0u};
+    ByteStream bs{b, sb, -K, 0u};  // row 1 compares b[-K .. K] (1-indexed j = 1 - K .. 1 + K)
+    uint64_t win = 0;
+#pragma unroll
+    for (int t = 0; t < W; ++t)
+        win |= (uint64_t)bs.next() << (8 * t);
     for (uint32_t i = 1; i <= m; ++i) {
-        const uint32_t ai = byte_at(a, i - 1);
+        const uint32_t ai = as.next();
         uint32_t rowmin = INF;
 #pragma unroll
         for (int t = 0; t < W; ++t) {
@@ -183,7 +252,8 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
             } else if (j == 0) {
                 v = min(i, INF);
             } else {
-                const uint32_t diag = prev[t] + (ai != byte_at(b, (uint32_t)j - 1) ? 1u : 0u);
+                const uint32_t bj = (uint32_t)(win >> (8 * t)) & 0xFFu;
+                const uint32_t diag = prev[t] + (ai != bj ? 1u : 0u);
                 const uint32_t up = (t + 1 < W) ? prev[t + 1] + 1u : INF;
                 const uint32_t left = (t >= 1) ? cur[t - 1] + 1u : INF;
                 v = min(min(diag, up), min(left, INF));
@@ -191,23 +261,25 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
             cur[t] = v;
             rowmin = min(rowmin, v);
         }
-        if (rowmin > (uint32_t)K)
+        if (!__any(rowmin <= (uint32_t)K))
             return K + 1;
 #pragma unroll
         for (int t = 0; t < W; ++t)
             prev[t] = cur[t];
+        win = (win >> 8) | ((uint64_t)bs.next() << (8 * (W - 1)));
     }
-    return prev[gap + K];
+    return min(prev[gap + K], INF);
 }
 
 template <int METRIC, int K>
-__device__ __forceinline__ uint32_t verify(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
+__device__ __forceinline__ uint32_t verify(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b, uint32_t sb,
+                                           uint32_t n)
 {
     if (METRIC == 0)
-        return verify_ham<K>(a, m, b, n);
+        return m == n ? verify_ham<K>(a, sa, b, sb, m) : K + 1;
     if (K == 1)
-        return verify_lev1(a, m, b, n);
-    return verify_lev_band<K>(a, m, b, n);
+        return verify_lev1(a, sa, m, b, sb, n);
+    return verify_lev_band<K>(a, sa, m, b, sb, n);
 }
 
 // Wave-uniform, read-only data (work list, query keys) is read through the
@@ -229,8 +301,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 // ---------------------------------------------------------- work items
 
 struct Item {
-    uint32_t qs, qn;  // sorted query range
-    uint32_t ds, de;  // sorted dictionary range
+    uint32_t qs, qn;        // sorted query range
+    uint32_t ds, de;        // sorted dictionary range
+    uint32_t m, L;          // query length, word length
+    uint32_t qslot, dslot;  // dword offsets of the first query / word slot
+    uint32_t qsw, dsw;      // slot sizes in dwords
 };
 
 __device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, uint32_t n_pairs)
@@ -254,57 +329,84 @@ __device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, u
     it.qn = min(a.qtile, qbase + nq - it.qs);
     it.ds = dbase + td * a.slab;
     it.de = min(it.ds + a.slab, dbase + nd);
+    it.m = pairs[lo].qlen;
+    it.L = pairs[lo].dlen;
+    it.qslot = as_const(a.q.soff)[it.qs];
+    it.dslot = as_const(a.d.soff)[it.ds];
+    it.qsw = slot_dwords(it.m);
+    it.dsw = slot_dwords(it.L);
     return it;
 }
 
+// Queue entries are item-relative: query offset in the tile (10 bits) and
+// word offset in the slab (22 bits).
+constexpr uint32_t kWordBits = 22;
+
+// Write the staged matches of a wave to the global match list.
+__device__ __forceinline__ void flush(const MatchArgs &a, const uint64_t *out, uint32_t &ocount, uint32_t lane)
+{
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0)
+        base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)ocount);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < ocount; i += 64) {
+        const uint64_t idx = base + i;
+        if (idx < a.out_cap)
+            a.out_keys[idx] = out[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    ocount = 0;
+}
+
 // Pop `nact` (<= 64) entries from the wave queue, verify one per lane and
-// emit matches.
+// stage the matches.
 template <int METRIC, int K>
-__device__ __forceinline__ void drain(const MatchArgs &a, const uint2 *queue, uint32_t &qlen, uint32_t nact,
-                                      uint32_t lane, uint64_t &cells)
+__device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const uint32_t *queue, uint32_t &qlen,
+                                      uint32_t nact, uint32_t lane, uint64_t &cells, uint64_t *out, uint32_t &ocount)
 {
     __builtin_amdgcn_wave_barrier();
     const bool act = lane < nact;
-    const uint2 ent = act ? queue[qlen - nact + lane] : make_uint2(0u, 0u);
+    const uint32_t ent = act ? queue[qlen - nact + lane] : 0u;
     __builtin_amdgcn_wave_barrier();
     qlen -= nact;
+    cells += (uint64_t)(2 * K + 1) * min(it.m, it.L) * nact;
+    const uint32_t tq = ent >> kWordBits, te = ent & ((1u << kWordBits) - 1u);
     uint32_t d = K + 1;
     if (act) {
-        const uint32_t m = a.q.len[ent.x], n = a.d.len[ent.y];
-        cells += (uint64_t)(2 * K + 1) * min(m, n);
-        d = a.survivors_only ? 0u : verify<METRIC, K>(a.q.str + a.q.soff[ent.x], m, a.d.str + a.d.soff[ent.y], n);
+        d = a.survivors_only ? 0u
+                             : verify<METRIC, K>(a.q.str + it.qslot + tq * it.qsw, it.qsw, it.m,
+                                                 a.d.str + it.dslot + te * it.dsw, it.dsw, it.L);
     }
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);
     if (mm) {
-        unsigned long long base = 0;
-        if (lane == (uint32_t)__builtin_ctzll(mm))
-            base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)__popcll(mm));
-        base = __shfl(base, (int)__builtin_ctzll(mm));
-        if (ok) {
-            const uint64_t idx = base + lanes_below(mm);
-            if (idx < a.out_cap)
-                a.out_keys[idx] = ((uint64_t)a.q.perm[ent.x] << (a.wbits + 2)) | ((uint64_t)a.d.perm[ent.y] << 2) | d;
-        }
+        if (ok)
+            out[ocount + lanes_below(mm)] = ((uint64_t)a.q.perm[it.qs + tq] << (a.wbits + 2)) |
+                                            ((uint64_t)a.d.perm[it.ds + te] << 2) | d;
+        ocount += (uint32_t)__popcll(mm);
+        if (ocount > (uint32_t)kOutFlush)
+            flush(a, out, ocount, lane);
     }
 }
 
 template <int KIND, int METRIC, int K, bool PERSISTENT>
-__global__ void __launch_bounds__(256) k_match(MatchArgs a)
+__global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 {
     using F = Filter<KIND>;
     using Key = typename F::Key;
-    __shared__ uint2 queue_all[kWaves][kQueueCap];
+    __shared__ uint32_t queue_all[kWaves][kQueueCap];
+    __shared__ uint64_t out_all[kWaves][kOutCap];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    uint2 *queue = queue_all[wave];
+    uint32_t *queue = queue_all[wave];
+    uint64_t *out = out_all[wave];
+    uint32_t ocount = 0;
     const cptr<Key> qkeys = as_const((const Key *)a.q.key);
     const Key *__restrict__ dkeys = (const Key *)a.d.key;
     const uint32_t neg = 0u - (2u * K + 1u);
     const uint32_t n_items = *as_const(a.wl.n_items);
     const uint32_t n_pairs = *as_const(a.wl.n_pairs);
-    uint32_t qlen = 0;
-    uint64_t survivors = 0;
-    uint64_t cells = 0;
+    uint64_t survivors = 0, cells = 0;
 
     uint32_t item;
     if (PERSISTENT) {
@@ -317,6 +419,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs a)
     }
     while (item < n_items) {
         const Item it = decode_item(a, item, n_pairs);
+        uint32_t qlen = 0;
         for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
             const uint32_t e = e0 + lane;
             const bool valid = e < it.de;
@@ -342,19 +445,21 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs a)
                         tot += (uint32_t)__popcll(m) << b;
                     }
                     uint32_t pos = qlen + pre;
-                    const uint32_t qbase = it.qs + j0 + (kChunk - 1);
+                    const uint32_t ent0 = ((j0 + kChunk - 1) << kWordBits) | (e - it.ds);
                     while (msk) {
                         const uint32_t bit = 31u - (uint32_t)__builtin_clz(msk);
-                        queue[pos++] = make_uint2(qbase - bit, e);
+                        queue[pos++] = ent0 - (bit << kWordBits);
                         msk &= ~(1u << bit);
                     }
                     qlen += tot;
                     survivors += tot;
                     while (qlen >= 64)
-                        drain<METRIC, K>(a, queue, qlen, 64, lane, cells);
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
                 }
             }
         }
+        if (qlen)
+            drain<METRIC, K>(a, it, queue, qlen, qlen, lane, cells, out, ocount);
         if (!PERSISTENT)
             break;
         uint32_t v = 0;
@@ -362,11 +467,8 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs a)
             v = atomicAdd(a.wl.counter, 1u);
         item = __builtin_amdgcn_readfirstlane(v);
     }
-    if (qlen)
-        drain<METRIC, K>(a, queue, qlen, qlen, lane, cells);
-    // per-wave counters
-    for (int off = 32; off >= 1; off >>= 1)
-        cells += __shfl_xor(cells, off);
+    if (ocount)
+        flush(a, out, ocount, lane);
     if (lane == 0) {
         if (survivors)
             atomicAdd((unsigned long long *)a.ctr.survivors, (unsigned long long)survivors);
@@ -452,7 +554,8 @@ __global__ void k_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
     if (i >= n)
         return;
     const uint32_t qi = qinv[pairs[2 * i]], wi = dinv[pairs[2 * i + 1]];
-    dist[i] = verify<METRIC, K>(q.str + q.soff[qi], q.len[qi], d.str + d.soff[wi], d.len[wi]);
+    const uint32_t lq = q.len[qi], lw = d.len[wi];
+    dist[i] = verify<METRIC, K>(q.str + q.soff[qi], slot_dwords(lq), lq, d.str + d.soff[wi], slot_dwords(lw), lw);
 }
 
 template <int KIND, int METRIC, int K>

@@ -45,29 +45,44 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_
     hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
 }
 
-// Exclusive scan of n entries in place, one block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v, uint32_t n)
+// Exclusive scan of the 256 x kRadixBlocks digit table in place, one block
+// of 1024 threads; each thread holds a contiguous run of PER entries in
+// registers (vector loads), so the table is read and written once.
+template <int PER>
+__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
 {
     __shared__ uint32_t part[1024];
     const uint32_t t = threadIdx.x;
-    const uint32_t per = (n + 1023) / 1024;
-    const uint32_t lo = t * per, hi = min(n, lo + per);
+    uint4 x[PER / 4];
+    uint4 *p = (uint4 *)(v + (size_t)t * PER);
+#pragma unroll
+    for (int i = 0; i < PER / 4; ++i)
+        x[i] = p[i];
     uint32_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i)
-        s += v[i];
+#pragma unroll
+    for (int i = 0; i < PER / 4; ++i)
+        s += x[i].x + x[i].y + x[i].z + x[i].w;
     part[t] = s;
     __syncthreads();
     for (uint32_t off = 1; off < 1024; off <<= 1) {
-        uint32_t x = t >= off ? part[t - off] : 0;
+        const uint32_t y = t >= off ? part[t - off] : 0;
         __syncthreads();
-        part[t] += x;
+        part[t] += y;
         __syncthreads();
     }
     uint32_t run = t ? part[t - 1] : 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        uint32_t x = v[i];
-        v[i] = run;
-        run += x;
+#pragma unroll
+    for (int i = 0; i < PER / 4; ++i) {
+        uint4 o;
+        o.x = run;
+        run += x[i].x;
+        o.y = run;
+        run += x[i].y;
+        o.z = run;
+        run += x[i].z;
+        o.w = run;
+        run += x[i].w;
+        p[i] = o;
     }
 }
 
@@ -130,7 +145,7 @@ __global__ void __launch_bounds__(256) k_bucket_tables(const uint32_t *offs, uin
     off[L] = start;
     if (L == 255)
         off[256] = n;
-    part[L] = (end - start) * slot_dwords(L);
+    part[L] = ((end - start) * slot_dwords(L) + 3u) & ~3u;  // 16-byte aligned blocks
     __syncthreads();
     for (uint32_t o = 1; o < 256; o <<= 1) {
         uint32_t x = L >= o ? part[L - o] : 0;
@@ -177,7 +192,8 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, cons
 {
     hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
-    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, scratch, 256u * kRadixBlocks);
+    static_assert(256 * kRadixBlocks % 4096 == 0, "scan table must split into 1024 runs of 4k entries");
+    hipLaunchKernelGGL(k_scan_exclusive<256 * kRadixBlocks / 1024>, dim3(1), dim3(1024), 0, s, scratch);
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64), 0, s, kin, vin, kout, vout, dcount, hcount,
                        cap, shift, scratch);
 }

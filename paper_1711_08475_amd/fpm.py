@@ -34,7 +34,7 @@ EXPORTS = [
     "fpm_last_error", "fpm_free", "fpm_num_fields", "fpm_select_symbols", "fpm_build_fingerprints",
     "fpm_index_destroy", "fpm_get_fingerprints", "fpm_get_map", "fpm_index_info", "fpm_fingerprints",
     "fpm_match", "fpm_filter_pairs", "fpm_verify_pairs", "fpm_plan_create", "fpm_plan_run", "fpm_plan_result",
-    "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune",
+    "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune", "fpm_plan_kernel_ms",
 ]
 
 
@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("queries_per_item", ctypes.c_uint32), ("slab", ctypes.c_uint32),
                 ("bucket_order", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
-                ("match_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 9)]
+                ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 8)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -113,6 +114,7 @@ def lib():
         "fpm_plan_result": (ctypes.c_int, [vp, ctypes.POINTER(vp), u64p, ctypes.POINTER(Stats)]),
         "fpm_plan_copy_matches": (ctypes.c_int, [vp, vp, ctypes.c_uint64, u64p]),
         "fpm_plan_destroy": (None, [vp]),
+        "fpm_plan_kernel_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_uint32, u32p]),
         "fpm_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Options),
                                         ctypes.POINTER(ctypes.c_float), ctypes.c_uint32, u32p]),
@@ -301,12 +303,21 @@ def fpm_plan_copy_matches(plan: Plan) -> np.ndarray:
     return out[: got.value]
 
 
+def fpm_plan_kernel_ms(plan: Plan, max_runs: int = 256) -> np.ndarray:
+    """Match-kernel durations (ms) of the last runs of a time_kernel plan."""
+    out = np.zeros(max(max_runs, 1), dtype=np.float32)
+    n = ctypes.c_uint32()
+    _check(lib().fpm_plan_kernel_ms(plan.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), max_runs,
+                                    ctypes.byref(n)))
+    return out[: n.value]
+
+
 def fpm_autotune(ix: Index, d_qbytes: int, d_qoffsets: int, n_queries: int, query_bytes: int, metric="lev",
                  k: int = 1, repeats: int = 3, base: Options | None = None):
     best = base if base is not None else Options()
-    tim = (ctypes.c_float * (4 * 64))()
+    tim = (ctypes.c_float * (4 * 128))()
     nt = ctypes.c_uint32()
     _check(lib().fpm_autotune(ix.handle, vp(d_qbytes), vp(d_qoffsets), n_queries, query_bytes,
-                              _code(METRICS, metric), k, repeats, ctypes.byref(best), tim, 64, ctypes.byref(nt)))
+                              _code(METRICS, metric), k, repeats, ctypes.byref(best), tim, 128, ctypes.byref(nt)))
     rows = [tuple(tim[4 * i:4 * i + 4]) for i in range(nt.value)]
     return best, rows

@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Lev k=1 query-word pairs/sec (1 MI355X), learned+batched vs plain filter"
 PEAK_INT_OPS = 256 * 64 * 2.4e9  # CUs x lanes x clock: one 32-bit VALU op per lane per clock
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_traffic.json")
+TUNING_FILE = os.path.join(ROOT, "paper_1711_08475_amd", "tuned.json")
 MATCH_SRC = os.path.join(ROOT, "paper_1711_08475_amd", "csrc", "fpm_match.hip")
 
 
@@ -59,6 +60,25 @@ def load_traffic():
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return t
+
+
+def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool):
+    """Autotuner result for `key`, from the tuning table when present (so a
+    profiled run dispatches the match kernel with one configuration only),
+    else measured now and stored."""
+    table = {}
+    if os.path.exists(TUNING_FILE):
+        table = json.load(open(TUNING_FILE))
+    if key in table and not retune:
+        return fpm.options(**table[key]), False
+    t = time.perf_counter()
+    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "lev", 1, 2)
+    log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s")
+    entry = {k: v for k, v in best.as_dict().items() if k in ("schedule", "queries_per_item", "slab", "bucket_order")}
+    table[key] = entry
+    with open(TUNING_FILE, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    return fpm.options(**entry), True
 
 
 def time_plan(fpm, torch, plan, qb, qo, nq, steps, warmup):
@@ -114,7 +134,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="plain,batched,brute")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="default tiles for the batched form")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even when the table has an entry")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
@@ -142,6 +165,14 @@ def main():
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
     qbytes = int(q[1][-1])
 
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_mib} MiB read + {args.copy_mib} MiB written")
+        del src, dst
+
     modes = args.modes.split(",")
     results = {}
     hits = {}
@@ -155,12 +186,11 @@ def main():
             if args.no_autotune:
                 opts = fpm.options(schedule=fpm.FPM_SCHED_BATCHED, time_kernel=1)
             else:
-                t = time.perf_counter()
-                best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "lev", 1, 2)
-                tuned = best.as_dict()
-                log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s -> {tuned}")
-                best.time_kernel = 1
-                opts = best
+                key = f"{args.workload}|{args.variant}{args.bits}|lev1|common"
+                opts, fresh = tuned_options(fpm, key, ix, qb, qo, nq, qbytes, args.retune)
+                tuned = opts.as_dict()
+                log(f"tiles ({'autotuned now' if fresh else 'tuning table'}): {tuned}")
+                opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
         plan = fpm.fpm_plan_create(ix, nq, qbytes, "lev", 1, opts)

@@ -16,7 +16,8 @@ Forms timed on the same GPU:
   brute        no fingerprints: every length-compatible pair is verified (the
                paper's naive comparison, giving its speedup S = T_n / T_f);
   learned      the batched form with the symbol grouping learned by the MLP
-               (when --learned is given or a learned map file exists).
+               (paper_1711_08475_amd/maps/<workload>_occ<bits>_k1.json, written by
+               `python -m paper_1711_08475_amd.learn`; --train retrains it here).
 
 Prints one JSON line.  `value` is the headline form's logical pairs/s
 (|Q| * |D| / step time).
@@ -50,14 +51,17 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(MATCH_SRC, "rb").read()).hexdigest()
 
 
-def load_traffic():
+def load_traffic(form: str, workload: str):
     """HBM bytes per launch of the match kernel from the committed rocprofv3
-    counter runs, only while the kernel source is unchanged since."""
+    counter runs of this form and workload, only while the kernel source is
+    unchanged since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if t.get("form") != form or t.get("workload_name") != workload:
         return None
     return t
 
@@ -133,7 +137,9 @@ def main():
     ap.add_argument("--bits", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="plain,batched,brute")
+    ap.add_argument("--modes", default="plain,brute,learned",
+                    help="forms to time, from plain, batched, brute, learned; the last one named is the headline")
+    ap.add_argument("--train", action="store_true", help="train the learned grouping in this process")
     ap.add_argument("--no-autotune", action="store_true", help="default tiles for the batched form")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even when the table has an entry")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -177,23 +183,37 @@ def main():
     results = {}
     hits = {}
     tuned = None
+    learned_meta = None
+    indexes = {"paper": ix}
+    if "learned" in modes:
+        from paper_1711_08475_amd import learn
+
+        name = f"{args.workload}_{args.variant}{args.bits}_k1"
+        mp, learned_meta = learn.load_map(name)
+        if mp is None or args.train:
+            t = time.perf_counter()
+            mp, rep = learn.learn_grouping(d, datagen.training_queries(args.workload), bits=args.bits, k=1)
+            learned_meta = {"training": rep, "chosen": "learned (trained in this run)"}
+            log(f"trained grouping in {time.perf_counter() - t:.1f} s")
+        indexes["learned"] = fpm.fpm_build_fingerprints(d, args.variant, args.bits, custom_map=mp)
     for mode in modes:
         if mode == "plain":
             opts = fpm.options(schedule=fpm.FPM_SCHED_PLAIN, time_kernel=1)
         elif mode == "brute":
             opts = fpm.options(schedule=fpm.FPM_SCHED_BRUTE, time_kernel=1)
-        elif mode == "batched":
+        elif mode in ("batched", "learned"):
+            mix = indexes["learned" if mode == "learned" else "paper"]
             if args.no_autotune:
                 opts = fpm.options(schedule=fpm.FPM_SCHED_BATCHED, time_kernel=1)
             else:
-                key = f"{args.workload}|{args.variant}{args.bits}|lev1|common"
-                opts, fresh = tuned_options(fpm, key, ix, qb, qo, nq, qbytes, args.retune)
+                key = f"{args.workload}|{args.variant}{args.bits}|lev1|{'learned' if mode == 'learned' else 'common'}"
+                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune)
                 tuned = opts.as_dict()
-                log(f"tiles ({'autotuned now' if fresh else 'tuning table'}): {tuned}")
+                log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {tuned}")
                 opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
-        plan = fpm.fpm_plan_create(ix, nq, qbytes, "lev", 1, opts)
+        plan = fpm.fpm_plan_create(indexes["learned" if mode == "learned" else "paper"], nq, qbytes, "lev", 1, opts)
         ms, n, st = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
         kms = fpm.fpm_plan_kernel_ms(plan, args.steps)
         results[mode] = {
@@ -211,12 +231,12 @@ def main():
     names = list(hits)
     agree = all(np.array_equal(hits[names[0]], hits[m]) for m in names[1:])
 
-    head = "batched" if "batched" in results else names[0]
+    head = names[-1]
     r = results[head]
     st = r["stats"]
     ops = 3 * st["pairs_examined"] + st["verify_cells"]
     achieved = ops / (r["kernel_ms"] * 1e-3) if r["kernel_ms"] else None
-    traffic = load_traffic()
+    traffic = load_traffic(head, args.workload)
     roofline = {
         "bound": "alu",
         "achieved": achieved / 1e12 if achieved else None,
@@ -255,7 +275,7 @@ def main():
             "workload": f"{args.workload}: {nd} English-like words x {nq} queries, Levenshtein k=1",
             "fingerprint": f"{args.variant}{args.bits}",
             "form": head,
-            "symbols": "common (paper map)",
+            "symbols": "learned grouping" if head == "learned" else "common (paper map)",
             "options": tuned,
         },
         "roofline": roofline,
@@ -266,6 +286,9 @@ def main():
                   for m, v in results.items()},
         "rejection_rate": 1.0 - st["survivors"] / max(st["pairs_examined"], 1),
         "speedup_vs_brute": (results["brute"]["ms_per_step"] / r["ms_per_step"]) if "brute" in results else None,
+        "speedup_vs_plain": (results["plain"]["ms_per_step"] / r["ms_per_step"]) if "plain" in results else None,
+        "learned_map": ({"chosen": learned_meta.get("chosen"), "evaluation": learned_meta.get("evaluation"),
+                         "train_ms": learned_meta.get("training", {}).get("ms")} if learned_meta else None),
         "forms_agree": agree,
         "sampled_oracle_parity": sampled_parity,
     }

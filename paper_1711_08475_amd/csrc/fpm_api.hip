@@ -15,15 +15,14 @@
 #include <vector>
 
 #include "../../include/fpm.h"
+#include "fpm_host.hpp"
 #include "fpm_internal.hpp"
 
 using namespace fpm;
 
-namespace {
+namespace fpm {
 
 thread_local std::string g_last_error;
-
-constexpr uint32_t kRing = 256;  // kernel-timing event pairs per plan
 
 fpm_status fail(fpm_status st, const char *fmt, ...)
 {
@@ -41,27 +40,11 @@ fpm_status hip_fail(hipError_t e, const char *what)
     return fail(e == hipErrorOutOfMemory ? FPM_ENOMEM : FPM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIPCHK(expr)                                   \
-    do {                                               \
-        hipError_t _e = (expr);                        \
-        if (_e != hipSuccess)                          \
-            return hip_fail(_e, #expr);                \
-    } while (0)
+}  // namespace fpm
 
-template <typename T>
-hipError_t dalloc(T **p, size_t count)
-{
-    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-    return hipMalloc((void **)p, bytes);
-}
+namespace {
 
-template <typename T>
-void dfree(T *&p)
-{
-    if (p)
-        (void)hipFree((void *)p);
-    p = nullptr;
-}
+constexpr uint32_t kRing = 256;  // kernel-timing event pairs per plan
 
 uint32_t bits_for(uint64_t n)  // bits to index 0..n-1 (at least 1)
 {

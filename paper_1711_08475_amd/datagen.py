@@ -222,32 +222,39 @@ def make_queries(dictionary, n: int, seed: int, rho: float, edit_choices, fresh,
 # near-match rates are the ones the benchmarks use)
 # --------------------------------------------------------------------------
 
-def english_workload(n_words: int, n_queries: int, seed: int, law: str, rho: float, edit_choices=(1,)):
+def english_workload(n_words: int, n_queries: int, seed: int, law: str, rho: float, edit_choices=(1,),
+                     query_seed: int | None = None):
+    """Dictionary from `seed`; queries from `query_seed` (default: `seed`)."""
+    qs = seed if query_seed is None else query_seed
     alpha = EnglishLike(seed)
     d = english_words(n_words, seed, law, alpha)
 
     def fresh(m, rng):
-        r2 = np.random.default_rng([seed, 0x53, int(rng.integers(1 << 30))])
+        r2 = np.random.default_rng([qs, 0x53, int(rng.integers(1 << 30))])
         return english_words(m, int(r2.integers(1 << 30)), law, alpha)
 
-    q = make_queries(d, n_queries, seed, rho, edit_choices, fresh, alpha.draw, min_len=2 if law == "2-20" else 3)
+    q = make_queries(d, n_queries, qs, rho, edit_choices, fresh, alpha.draw, min_len=2 if law == "2-20" else 3)
     return d, q
 
 
-def url_workload(n_words: int, n_queries: int, seed: int, rho: float = 0.3, edit_choices=(1, 2)):
+def url_workload(n_words: int, n_queries: int, seed: int, rho: float = 0.3, edit_choices=(1, 2),
+                 query_seed: int | None = None):
+    qs = seed if query_seed is None else query_seed
     gen = UrlLike(seed)
     d = url_strings(n_words, seed, gen)
 
     def fresh(m, rng):
         return to_csr(gen.urls(m, rng))
 
-    q = make_queries(d, n_queries, seed, rho, edit_choices, fresh, gen.draw_symbols, min_len=20)
+    q = make_queries(d, n_queries, qs, rho, edit_choices, fresh, gen.draw_symbols, min_len=20)
     return d, q
 
 
-def mixed_workload(n_english: int, n_urls: int, n_queries: int, seed: int, rho: float = 0.3):
+def mixed_workload(n_english: int, n_urls: int, n_queries: int, seed: int, rho: float = 0.3,
+                   query_seed: int | None = None):
     """English-like (lengths 2-20) and URL-like (20-120) strings mixed 1:1 and
     shuffled; queries drawn the same way from both halves."""
+    qs = seed if query_seed is None else query_seed
     alpha = EnglishLike(seed)
     gen = UrlLike(seed)
     de = english_words(n_english, seed, "2-20", alpha)
@@ -256,27 +263,39 @@ def mixed_workload(n_english: int, n_urls: int, n_queries: int, seed: int, rho: 
     both = concat_csr(de, du)
     perm = rng.permutation(n_english + n_urls)
     d = take_csr(both, perm)
-    qe = make_queries(de, n_queries // 2, seed + 11, rho, (1,),
+    qe = make_queries(de, n_queries // 2, qs + 11, rho, (1,),
                       lambda m, r: english_words(m, int(r.integers(1 << 30)), "2-20", alpha), alpha.draw, 2)
-    qu = make_queries(du, n_queries - n_queries // 2, seed + 13, rho, (1,),
+    qu = make_queries(du, n_queries - n_queries // 2, qs + 13, rho, (1,),
                       lambda m, r: to_csr(gen.urls(m, r)), gen.draw_symbols, 20)
     qb = concat_csr(qe, qu)
-    qperm = rng.permutation(n_queries)
+    qperm = np.random.default_rng([qs, 0x4E]).permutation(n_queries) if query_seed is not None \
+        else rng.permutation(n_queries)
     return d, take_csr(qb, qperm)
 
 
 WORKLOADS = {
     # 10,000 English-like words (lengths 3-15) x 1,000 queries, half near-matches
-    "english_10k_q1k": lambda seed=1: english_workload(10_000, 1_000, seed, "3-15", 0.5),
+    "english_10k_q1k": (1, lambda seed, qs: english_workload(10_000, 1_000, seed, "3-15", 0.5, query_seed=qs)),
     # 1,000,000 English-like words (lengths 2-20) x 10,000 queries, 30% near-matches
-    "english_1m_q10k": lambda seed=2: english_workload(1_000_000, 10_000, seed, "2-20", 0.3),
+    "english_1m_q10k": (2, lambda seed, qs: english_workload(1_000_000, 10_000, seed, "2-20", 0.3, query_seed=qs)),
     # 1,000,000 URL-like strings x 10,000 queries, 30% near-matches with 1 or 2 edits
-    "url_1m_q10k": lambda seed=3: url_workload(1_000_000, 10_000, seed, 0.3, (1, 2)),
+    "url_1m_q10k": (3, lambda seed, qs: url_workload(1_000_000, 10_000, seed, 0.3, (1, 2), query_seed=qs)),
     # 2,000,000 mixed English/URL strings x 65,536 mixed queries
-    "mixed_2m_q64k": lambda seed=4: mixed_workload(1_000_000, 1_000_000, 65_536, seed),
+    "mixed_2m_q64k": (4, lambda seed, qs: mixed_workload(1_000_000, 1_000_000, 65_536, seed, query_seed=qs)),
 }
 
+TRAINING_QUERY_SEED_OFFSET = 1000
 
-def workload(name: str, seed: int | None = None):
-    f = WORKLOADS[name]
-    return f() if seed is None else f(seed)
+
+def workload(name: str, seed: int | None = None, query_seed: int | None = None):
+    """(dictionary, queries) of a named workload."""
+    default_seed, f = WORKLOADS[name]
+    return f(default_seed if seed is None else seed, query_seed)
+
+
+def training_queries(name: str):
+    """Queries of workload `name` drawn with another seed (same dictionary,
+    same query recipe): what a learned grouping is trained on, so the
+    workload's own queries stay held out."""
+    default_seed, f = WORKLOADS[name]
+    return f(default_seed, default_seed + TRAINING_QUERY_SEED_OFFSET)[1]

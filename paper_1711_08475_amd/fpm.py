@@ -36,6 +36,8 @@ EXPORTS = [
     "fpm_match", "fpm_filter_pairs", "fpm_verify_pairs", "fpm_plan_create", "fpm_plan_run", "fpm_plan_result",
     "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune", "fpm_plan_kernel_ms",
 ]
+# every symbol include/fpm_learn.h declares
+LEARN_EXPORTS = ["fpm_learn_grouping", "fpm_learn_step"]
 
 
 class FpmError(RuntimeError):
@@ -65,6 +67,23 @@ class Options(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class LearnConfig(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_uint32), ("k", ctypes.c_uint32), ("hidden", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("margin", ctypes.c_float), ("beta", ctypes.c_float), ("entropy_weight", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class LearnReport(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_uint32), ("d_in", ctypes.c_uint32), ("n_params", ctypes.c_uint32),
+                ("steps", ctypes.c_uint32), ("train_pairs", ctypes.c_uint64), ("first_loss", ctypes.c_float),
+                ("final_loss", ctypes.c_float), ("final_entropy", ctypes.c_float), ("expected_fd", ctypes.c_float),
+                ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def options(**kw) -> Options:
@@ -119,6 +138,13 @@ def lib():
                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Options),
                                         ctypes.POINTER(ctypes.c_float), ctypes.c_uint32, u32p]),
     }
+    fp = ctypes.POINTER(ctypes.c_float)
+    sig["fpm_learn_grouping"] = (ctypes.c_int, [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, u32p, u8p,
+                                                ctypes.c_uint64, ctypes.POINTER(LearnConfig), u8p,
+                                                ctypes.POINTER(LearnReport)])
+    sig["fpm_learn_step"] = (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, fp, fp, u64p, u64p, ctypes.c_uint64, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, fp, fp, fp])
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
@@ -321,3 +347,40 @@ def fpm_autotune(ix: Index, d_qbytes: int, d_qoffsets: int, n_queries: int, quer
                               _code(METRICS, metric), k, repeats, ctypes.byref(best), tim, 128, ctypes.byref(nt)))
     rows = [tuple(tim[4 * i:4 * i + 4]) for i in range(nt.value)]
     return best, rows
+
+
+# ------------------------------------------------------------ learned grouping
+
+def fpm_learn_grouping(dictionary, queries, pairs: np.ndarray, is_match: np.ndarray, cfg: LearnConfig):
+    """(map uint8[256], report dict)."""
+    db, do = _csr(dictionary)
+    qb, qo = _csr(queries)
+    p = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    m = np.ascontiguousarray(is_match, dtype=np.uint8)
+    if p.shape[0] == 0:
+        p = np.zeros((1, 2), dtype=np.uint32)[:0]
+    out = np.zeros(256, dtype=np.uint8)
+    rep = LearnReport()
+    _check(lib().fpm_learn_grouping(_p(db, ctypes.c_uint8), _p(do, ctypes.c_uint64), do.size - 1,
+                                    _p(qb, ctypes.c_uint8), _p(qo, ctypes.c_uint64), qo.size - 1,
+                                    _p(np.ascontiguousarray(p), ctypes.c_uint32), _p(m, ctypes.c_uint8), p.shape[0],
+                                    ctypes.byref(cfg), _p(out, ctypes.c_uint8), ctypes.byref(rep)))
+    return out, rep.as_dict()
+
+
+def fpm_learn_step(X, params, hidden: int, bits: int, k: int, masks_a, masks_b, margin: float, beta: float,
+                   entropy_weight: float):
+    """One GPU forward/backward: (P, [pair loss, entropy, mean E], grads)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    prm = np.ascontiguousarray(params, dtype=np.float32)
+    ma = np.ascontiguousarray(masks_a, dtype=np.uint64).reshape(-1, 2)
+    mb = np.ascontiguousarray(masks_b, dtype=np.uint64).reshape(-1, 2)
+    sigma, d_in = X.shape
+    P = np.zeros((sigma, bits + 1), dtype=np.float32)
+    loss = np.zeros(3, dtype=np.float32)
+    g = np.zeros_like(prm)
+    fp = ctypes.c_float
+    _check(lib().fpm_learn_step(sigma, d_in, hidden, bits, k, _p(X, fp), _p(prm, fp), _p(ma, ctypes.c_uint64),
+                                _p(mb, ctypes.c_uint64), ma.shape[0], margin, beta, entropy_weight, _p(P, fp),
+                                _p(loss, fp), _p(g, fp)))
+    return P, loss, g

@@ -24,9 +24,12 @@ def test_header_declares_the_boundary():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libfpm.so not built")
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header", ["fpm.h", "fpm_learn.h"])
+def test_library_exports_every_declared_symbol(header):
     lib = ctypes.CDLL(LIB)
-    missing = [n for n in declared("fpm.h") if not hasattr(lib, n)]
+    names = declared(header)
+    assert names
+    missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
 
@@ -35,7 +38,8 @@ def test_binding_names_match_header():
     from paper_1711_08475_amd import fpm
 
     assert sorted(fpm.EXPORTS) == declared("fpm.h")
-    for n in fpm.EXPORTS:
+    assert sorted(fpm.LEARN_EXPORTS) == declared("fpm_learn.h")
+    for n in fpm.EXPORTS + fpm.LEARN_EXPORTS:
         if n in ("fpm_last_error", "fpm_free", "fpm_index_destroy", "fpm_plan_destroy"):
             continue
         assert callable(getattr(fpm, n)), n

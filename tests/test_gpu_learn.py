@@ -1,0 +1,110 @@
+"""GPU tests of the learned grouping: the training kernels against the float64
+reference, soundness of learned maps re-proved by the oracle, and the gain
+over the paper's fixed map on held-out queries."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learn_ref
+from paper_1711_08475_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fpm(gpu):
+    from paper_1711_08475_amd import fpm as f
+
+    f.lib()
+    return f
+
+
+def random_problem(seed, sigma, hidden, bits, n, density=0.3):
+    rng = np.random.default_rng(seed)
+    d_in = sigma + 4
+    X = np.concatenate([np.eye(sigma), rng.random((sigma, 4))], axis=1)
+    params = rng.normal(0, 0.3, learn_ref.n_params(d_in, hidden, bits))
+    A = rng.random((n, sigma)) < density
+    B = rng.random((n, sigma)) < density
+    ma = np.zeros((n, 2), dtype=np.uint64)
+    mb = np.zeros((n, 2), dtype=np.uint64)
+    for c in range(sigma):
+        w, b = divmod(c, 64)
+        ma[:, w] |= A[:, c].astype(np.uint64) << np.uint64(b)
+        mb[:, w] |= B[:, c].astype(np.uint64) << np.uint64(b)
+    return X, params, A.astype(float), B.astype(float), ma, mb
+
+
+@pytest.mark.parametrize("sigma,hidden,bits,k,n", [(20, 64, 16, 1, 3000), (72, 64, 32, 1, 2000),
+                                                   (26, 32, 16, 2, 1500), (100, 128, 32, 2, 500)])
+def test_training_step_matches_float64_reference(fpm, sigma, hidden, bits, k, n):
+    say("learn step", sigma, hidden, bits, k, n)
+    X, params, A, B, ma, mb = random_problem(sigma + bits, sigma, hidden, bits, n)
+    args = (hidden, bits, A, B, k, 0.5, 2.0, 0.05)
+    P, loss, g = fpm.fpm_learn_step(X, params, hidden, bits, k, ma, mb, 0.5, 2.0, 0.05)
+    _, _, Pr, _ = learn_ref.forward(X, params, hidden, bits)
+    pl, ent, e_mean, _ = learn_ref.loss(X, params, *args)
+    gr = learn_ref.grads(X, params, *args)
+    assert np.allclose(P, Pr, rtol=1e-5, atol=1e-6)
+    assert np.isclose(loss[0], pl, rtol=1e-4)
+    assert np.isclose(loss[1], ent, rtol=1e-4)
+    assert np.isclose(loss[2], e_mean, rtol=1e-4)
+    # FP32 sums over the pairs in a different order: tolerance relative to the gradient scale
+    assert np.abs(g - gr).max() <= 1e-4 * max(np.abs(gr).max(), 1e-6)
+
+
+def test_learned_grouping_is_sound_and_beats_the_paper_map(fpm):
+    """Train on verifier-labelled pairs of training queries, then on the
+    workload's own (held-out) queries: the match list equals the oracle's and
+    the filter rejects more pairs than with the paper's common map."""
+    from paper_1711_08475_amd import learn
+
+    d, q = datagen.workload("english_10k_q1k")
+    tq = datagen.training_queries("english_10k_q1k")
+    say("train grouping on english_10k_q1k")
+    cfg = learn.config(bits=16, k=1, epochs=40, seed=3)
+    mp, rep = learn.learn_grouping(d, tq, bits=16, k=1, n_pairs=400_000, seed=3, cfg=cfg)
+    assert rep["final_loss"] < rep["first_loss"]
+    assert all(int(x) == 255 or int(x) < 16 for x in mp)
+    assert oracle.check_map(mp, oracle.OCC, 16)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=mp)
+    # soundness re-proved by the oracle: identical match lists
+    for metric, k in [(oracle.LEV, 1), (oracle.HAM, 1), (oracle.LEV, 2)]:
+        assert np.array_equal(fpm.fpm_match(ix, q, metric, k), oracle.match(d, q, metric, k))
+    # the gain, with the oracle's own F_D counts on the held-out queries
+    paper = oracle.select_symbols(oracle.histogram(d), oracle.OCC, 16, oracle.COMMON)
+    ex_p, surv_p, _ = oracle.filter_stats(d, q, oracle.OCC, 16, paper, oracle.LEV, 1)
+    ex_l, surv_l, _ = oracle.filter_stats(d, q, oracle.OCC, 16, mp, oracle.LEV, 1)
+    assert ex_p == ex_l
+    say("rejection paper", 1 - surv_p / ex_p, "learned", 1 - surv_l / ex_l)
+    assert surv_l < surv_p
+    ev = learn.evaluate(d, q, mp, bits=16, k=1)
+    assert ev["learned_survivors"] == surv_l and ev["paper_survivors"] == surv_p
+
+
+def test_stored_map_claims_hold(fpm):
+    """The committed grouping of the benchmark workload: valid, its stored
+    evaluation reproduces on the GPU, and the sampled match list equals the
+    oracle's."""
+    from paper_1711_08475_amd import learn
+
+    mp, meta = learn.load_map("english_1m_q10k_occ16_k1")
+    if mp is None:
+        pytest.skip("no stored grouping")
+    assert oracle.check_map(mp, oracle.OCC, 16)
+    d, q = datagen.workload("english_1m_q10k")
+    say("stored map evaluation")
+    ev = learn.evaluate(d, q, mp, bits=16, k=1)
+    if meta["chosen"] == "learned":
+        assert ev["learned_survivors"] == meta["evaluation"]["learned_survivors"]
+        assert ev["learned_rejection"] > ev["paper_rejection"]
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=mp)
+    sample = np.arange(0, q[1].size - 1, 97)[:64]
+    qs = datagen.take_csr(q, sample)
+    got = fpm.fpm_match(ix, qs, "lev", 1)
+    ref = oracle.match(d, qs, oracle.LEV, 1, length_pruned=True)
+    assert np.array_equal(got, ref)

@@ -36,8 +36,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "Lev k=1 query-word pairs/sec (1 MI355X), learned+batched vs plain filter"
+WORKLOAD_TEXT = {
+    "english_10k_q1k": "10,000 English-like words (lengths 3-15) x 1,000 queries",
+    "english_1m_q10k": "1,000,000 English-like words (lengths 2-20) x 10,000 queries",
+    "url_1m_q10k": "1,000,000 URL-like strings (lengths 20-120) x 10,000 queries",
+    "mixed_2m_q64k": "2,000,000 mixed English-like/URL-like strings x 65,536 mixed queries",
+}
+
+
+def metric_name(metric: str, k: int) -> str:
+    return f"{'Lev' if metric == 'lev' else 'Ham'} k={k} query-word pairs/sec (1 MI355X), learned+batched vs plain filter"
 PEAK_INT_OPS = 256 * 64 * 2.4e9  # CUs x lanes x clock: one 32-bit VALU op per lane per clock
+# VALU instructions per examined pair in the filter loop (see fpm_match.hip)
+FILTER_OPS = {("occ", 16): 3, ("occ", 32): 3, ("occh", 16): 3, ("occh", 32): 3, ("count", 16): 3, ("count", 32): 5,
+              ("pos", 16): 8, ("pos", 32): 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_traffic.json")
 TUNING_FILE = os.path.join(ROOT, "paper_1711_08475_amd", "tuned.json")
 MATCH_SRC = os.path.join(ROOT, "paper_1711_08475_amd", "csrc", "fpm_match.hip")
@@ -66,7 +78,7 @@ def load_traffic(form: str, workload: str):
     return t
 
 
-def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool):
+def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int):
     """Autotuner result for `key`, from the tuning table when present (so a
     profiled run dispatches the match kernel with one configuration only),
     else measured now and stored."""
@@ -76,7 +88,7 @@ def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool):
     if key in table and not retune:
         return fpm.options(**table[key]), False
     t = time.perf_counter()
-    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "lev", 1, 2)
+    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2)
     log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s")
     entry = {k: v for k, v in best.as_dict().items() if k in ("schedule", "queries_per_item", "slab", "bucket_order")}
     table[key] = entry
@@ -99,7 +111,7 @@ def time_plan(fpm, torch, plan, qb, qo, nq, steps, warmup):
     return (t1 - t0) * 1e3 / steps, n, st
 
 
-def cpu_baseline(oracle, d, q, target_s: float):
+def cpu_baseline(oracle, d, q, target_s: float, metric: int, k: int):
     """The oracle (full DP on every pair, all host threads) on a bounded
     sample of the queries against the whole dictionary."""
     from paper_1711_08475_amd import datagen
@@ -109,20 +121,21 @@ def cpu_baseline(oracle, d, q, target_s: float):
     nd = d[1].size - 1
     cal = min(nq, threads)
     t0 = time.perf_counter()
-    oracle.match(d, datagen.take_csr(q, np.arange(cal)), oracle.LEV, 1, threads=threads)
+    oracle.match(d, datagen.take_csr(q, np.arange(cal)), metric, k, threads=threads)
     t_cal = time.perf_counter() - t0
     rounds = max(1, int(target_s / max(t_cal, 1e-3)))
     n_sample = int(min(nq, cal * rounds))
     idx = np.arange(n_sample)
     t0 = time.perf_counter()
-    res = oracle.match(d, datagen.take_csr(q, idx), oracle.LEV, 1, threads=threads)
+    res = oracle.match(d, datagen.take_csr(q, idx), metric, k, threads=threads)
     el = time.perf_counter() - t0
     return {
         "value": n_sample * nd / el,
         "unit": "pairs/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"first {n_sample} queries x all {nd} words, full Wagner-Fischer table on every pair, "
+        "sample": f"first {n_sample} queries x all {nd} words, "
+                  f"{'full Wagner-Fischer table' if metric == oracle.LEV else 'full mismatch count'} on every pair, "
                   f"{el:.1f} s",
     }, idx, res
 
@@ -135,6 +148,8 @@ def main():
     ap.add_argument("--workload", default="english_1m_q10k")
     ap.add_argument("--variant", default="occ")
     ap.add_argument("--bits", type=int, default=16)
+    ap.add_argument("--metric", default="lev", choices=["lev", "ham"])
+    ap.add_argument("-k", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="plain,brute,learned",
@@ -169,6 +184,7 @@ def main():
     log(f"index built in {time.perf_counter() - t:.2f} s")
     qb = torch.from_numpy(q[0].copy()).cuda()
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()  # the plans run on their own streams
     qbytes = int(q[1][-1])
 
     if args.copy_mib:
@@ -188,11 +204,11 @@ def main():
     if "learned" in modes:
         from paper_1711_08475_amd import learn
 
-        name = f"{args.workload}_{args.variant}{args.bits}_k1"
+        name = f"{args.workload}_{args.variant}{args.bits}_k{args.k}"
         mp, learned_meta = learn.load_map(name)
         if mp is None or args.train:
             t = time.perf_counter()
-            mp, rep = learn.learn_grouping(d, datagen.training_queries(args.workload), bits=args.bits, k=1)
+            mp, rep = learn.learn_grouping(d, datagen.training_queries(args.workload), bits=args.bits, k=args.k)
             learned_meta = {"training": rep, "chosen": "learned (trained in this run)"}
             log(f"trained grouping in {time.perf_counter() - t:.1f} s")
         indexes["learned"] = fpm.fpm_build_fingerprints(d, args.variant, args.bits, custom_map=mp)
@@ -206,14 +222,16 @@ def main():
             if args.no_autotune:
                 opts = fpm.options(schedule=fpm.FPM_SCHED_BATCHED, time_kernel=1)
             else:
-                key = f"{args.workload}|{args.variant}{args.bits}|lev1|{'learned' if mode == 'learned' else 'common'}"
-                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune)
+                key = (f"{args.workload}|{args.variant}{args.bits}|{args.metric}{args.k}|"
+                       f"{'learned' if mode == 'learned' else 'common'}")
+                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune, args.metric, args.k)
                 tuned = opts.as_dict()
                 log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {tuned}")
                 opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
-        plan = fpm.fpm_plan_create(indexes["learned" if mode == "learned" else "paper"], nq, qbytes, "lev", 1, opts)
+        plan = fpm.fpm_plan_create(indexes["learned" if mode == "learned" else "paper"], nq, qbytes, args.metric,
+                                   args.k, opts)
         ms, n, st = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
         kms = fpm.fpm_plan_kernel_ms(plan, args.steps)
         results[mode] = {
@@ -234,7 +252,7 @@ def main():
     head = names[-1]
     r = results[head]
     st = r["stats"]
-    ops = 3 * st["pairs_examined"] + st["verify_cells"]
+    ops = FILTER_OPS[(args.variant, args.bits)] * st["pairs_examined"] + st["verify_cells"]
     achieved = ops / (r["kernel_ms"] * 1e-3) if r["kernel_ms"] else None
     traffic = load_traffic(head, args.workload)
     roofline = {
@@ -252,14 +270,15 @@ def main():
     cpu = None
     sampled_parity = None
     if not args.no_cpu_baseline:
-        cpu, idx, ref = cpu_baseline(oracle, d, q, args.cpu_seconds)
+        cpu, idx, ref = cpu_baseline(oracle, d, q, args.cpu_seconds, oracle.LEV if args.metric == "lev" else oracle.HAM,
+                                     args.k)
         g = hits[head]
         g = g[np.isin(g[:, 0], idx)]
         sampled_parity = bool(np.array_equal(g, ref))
         log(f"cpu baseline {cpu['value']:.3e} pairs/s on {cpu['cores']} threads; sampled parity {sampled_parity}")
 
     out = {
-        "metric": METRIC,
+        "metric": metric_name(args.metric, args.k),
         "value": r["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -272,7 +291,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {nd} English-like words x {nq} queries, Levenshtein k=1",
+            "workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, args.workload)}, "
+                        f"{'Levenshtein' if args.metric == 'lev' else 'Hamming'} k={args.k}",
             "fingerprint": f"{args.variant}{args.bits}",
             "form": head,
             "symbols": "learned grouping" if head == "learned" else "common (paper map)",

@@ -106,24 +106,28 @@ struct Filter<kAll> {
 // branches on lengths are uniform; strings are read from their padded slots
 // 16 bytes at a time.
 
-// Dwords 4c..4c+3 of a string in a slot of sw dwords (1, 2 or a multiple of
-// 4, aligned to its size), zero beyond the slot.  sw and c are uniform.
-__device__ __forceinline__ uint4 chunk(const uint32_t *p, uint32_t sw, uint32_t c)
+// Dwords g0 .. g0+D-1 of a string (load_raw), then bytes at positions >=
+// len cleared (mask_tail).  The verifiers issue every load of a step before
+// any mask (one memory round trip); loads may run up to four dwords past
+// the string's slot, which the string buffers' tail slack covers.  len is
+// wave-uniform in the match kernel, so the masks are scalar.
+template <int D>
+__device__ __forceinline__ void load_raw(const uint32_t *p, uint32_t g0, uint32_t (&v)[D])
 {
-    if (sw >= 4)
-        return (4 * c < sw) ? *(const uint4 *)(p + 4 * c) : make_uint4(0u, 0u, 0u, 0u);
-    if (c)
-        return make_uint4(0u, 0u, 0u, 0u);
-    if (sw == 2) {
-        const uint2 v = *(const uint2 *)p;
-        return make_uint4(v.x, v.y, 0u, 0u);
-    }
-    return make_uint4(p[0], 0u, 0u, 0u);
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        v[t] = p[g0 + t];
 }
 
-__device__ __forceinline__ uint32_t dword_of(const uint4 &v, int t)
+template <int D>
+__device__ __forceinline__ void mask_tail(uint32_t g0, uint32_t len, uint32_t (&v)[D])
 {
-    return t == 0 ? v.x : t == 1 ? v.y : t == 2 ? v.z : v.w;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int rem = (int)len - 4 * (int)(g0 + t);
+        const uint32_t bits = 8u * (uint32_t)min(max(rem, 0), 4);
+        v[t] &= (uint32_t)((1ull << bits) - 1ull);
+    }
 }
 
 // number of nonzero bytes of x
@@ -132,66 +136,97 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
     return (uint32_t)__builtin_popcount((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
 }
 
+template <int D>
+__device__ __forceinline__ uint32_t ham_dwords(const uint32_t *a, const uint32_t *b, uint32_t g0, uint32_t m)
+{
+    uint32_t A[D], B[D];
+    load_raw<D>(a, g0, A);
+    load_raw<D>(b, g0, B);
+    mask_tail<D>(g0, m, A);
+    mask_tail<D>(g0, m, B);
+    uint32_t d = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        d += nz_bytes(A[t] ^ B[t]);
+    return d;
+}
+
 // Hamming distance of two strings of length m, capped at K + 1.
 template <int K>
-__device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, uint32_t sa, const uint32_t *b, uint32_t sb,
-                                               uint32_t m)
+__device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, const uint32_t *b, uint32_t m)
 {
-    const uint32_t nch = (m + 15) >> 4;
-    uint32_t d = 0;
-    for (uint32_t c = 0; c < nch; ++c) {
-        const uint4 A = chunk(a, sa, c), B = chunk(b, sb, c);
-        d += nz_bytes(A.x ^ B.x) + nz_bytes(A.y ^ B.y) + nz_bytes(A.z ^ B.z) + nz_bytes(A.w ^ B.w);
-        if (!__any(d <= (uint32_t)K))
-            break;
+    uint32_t d;
+    if (m <= 4) {
+        d = ham_dwords<1>(a, b, 0, m);
+    } else if (m <= 8) {
+        d = ham_dwords<2>(a, b, 0, m);
+    } else {
+        d = 0;
+        const uint32_t nch = (m + 15) >> 4;
+        for (uint32_t c = 0; c < nch; ++c) {
+            d += ham_dwords<4>(a, b, 4 * c, m);
+            if (!__any(d <= (uint32_t)K))
+                break;
+        }
     }
     return min(d, (uint32_t)K + 1);
+}
+
+// One group of D dwords of the Lev k = 1 test for lengths m and n = m + 1
+// (a shorter): first_a tracks the first j with a[j] != b[j] (clamped to m),
+// last_b the last j with a[j] != b[j + 1].
+template <int D>
+__device__ __forceinline__ void lev1_dwords(const uint32_t *a, const uint32_t *b, uint32_t g0, uint32_t m,
+                                            uint32_t &first_a, int &last_b)
+{
+    uint32_t A[D], B[D + 1];
+    load_raw<D>(a, g0, A);
+    load_raw<D + 1>(b, g0, B);
+    mask_tail<D>(g0, m, A);
+    mask_tail<D + 1>(g0, m + 1, B);
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const uint32_t xa = A[t] ^ B[t];
+        const uint32_t xb = A[t] ^ __builtin_amdgcn_alignbyte(B[t + 1], B[t], 1);
+        const uint32_t pos = 4 * (g0 + t);
+        if (first_a == m && xa != 0u)
+            first_a = min(pos + ((uint32_t)__builtin_ctz(xa) >> 3), m);
+        if (xb != 0u)
+            last_b = (int)(pos + ((31u - (uint32_t)__builtin_clz(xb)) >> 3));
+    }
 }
 
 // Levenshtein distance <= 1 test.  Equal lengths: Hamming <= 1.  Lengths m
 // and m + 1: with a the shorter string and b the longer one, b becomes a by
 // deleting one symbol iff every position j with a[j] != b[j + 1] lies before
 // the first position with a[j] != b[j] (then delete b at that position).
-__device__ __forceinline__ uint32_t verify_lev1(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b,
-                                                uint32_t sb, uint32_t n)
+__device__ __forceinline__ uint32_t verify_lev1(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
 {
     if (m == n)
-        return verify_ham<1>(a, sa, b, sb, m);
+        return verify_ham<1>(a, b, m);
     if (m > n) {
         const uint32_t *t = a;
         a = b;
         b = t;
-        uint32_t u = sa;
-        sa = sb;
-        sb = u;
-        u = m;
+        const uint32_t u = m;
         m = n;
         n = u;
     }
     if (n - m != 1)
         return 2;
-    const uint32_t nch = (m + 15) >> 4;
-    uint32_t first_a = m;  // first j with a[j] != b[j], clamped to m
-    int last_b = -1;       // last j with a[j] != b[j + 1]
-    uint4 B = chunk(b, sb, 0);
-    for (uint32_t c = 0; c < nch; ++c) {
-        const uint4 A = chunk(a, sa, c);
-        const uint4 Bn = chunk(b, sb, c + 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint32_t ai = dword_of(A, t), bi = dword_of(B, t);
-            const uint32_t bn = t < 3 ? dword_of(B, t + 1) : Bn.x;
-            const uint32_t xa = ai ^ bi;
-            const uint32_t xb = ai ^ __builtin_amdgcn_alignbyte(bn, bi, 1);
-            const uint32_t pos = 16 * c + 4 * t;
-            if (first_a == m && xa != 0u)
-                first_a = min(pos + ((uint32_t)__builtin_ctz(xa) >> 3), m);
-            if (xb != 0u)
-                last_b = (int)(pos + ((31u - (uint32_t)__builtin_clz(xb)) >> 3));
+    uint32_t first_a = m;
+    int last_b = -1;
+    if (m <= 4) {
+        lev1_dwords<1>(a, b, 0, m, first_a, last_b);
+    } else if (m <= 8) {
+        lev1_dwords<2>(a, b, 0, m, first_a, last_b);
+    } else {
+        const uint32_t nch = (m + 15) >> 4;
+        for (uint32_t c = 0; c < nch; ++c) {
+            lev1_dwords<4>(a, b, 4 * c, m, first_a, last_b);
+            if (!__any(last_b < (int)first_a))
+                break;
         }
-        if (!__any(last_b < (int)first_a))
-            break;
-        B = Bn;
     }
     return last_b < (int)first_a ? 1u : 2u;
 }
@@ -220,8 +255,7 @@ struct ByteStream {
 // j = i - K .. i + K; `win` holds the symbols b[j - 1] those cells compare,
 // byte t for j = i + t - K.
 template <int K>
-__device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b,
-                                                    uint32_t sb, uint32_t n)
+__device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
 {
     const int gap = (int)n - (int)m;
     if (gap > K || gap < -K)
@@ -234,8 +268,8 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
         const int j = t - K;
         prev[t] = (j >= 0 && j <= (int)n) ? min((uint32_t)j, INF) : INF;
     }
-    ByteStream as{a, sa, 0, 0u};
-    ByteStream bs{b, sb, -K, 0u};  // row 1 compares b[-K .. K] (1-indexed j = 1 - K .. 1 + K)
+    ByteStream as{a, (m + 3) >> 2, 0, 0u};
+    ByteStream bs{b, (n + 3) >> 2, -K, 0u};  // row 1 compares b[-K .. K] (1-indexed j = 1 - K .. 1 + K)
     uint64_t win = 0;
 #pragma unroll
     for (int t = 0; t < W; ++t)
@@ -272,14 +306,13 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
 }
 
 template <int METRIC, int K>
-__device__ __forceinline__ uint32_t verify(const uint32_t *a, uint32_t sa, uint32_t m, const uint32_t *b, uint32_t sb,
-                                           uint32_t n)
+__device__ __forceinline__ uint32_t verify(const uint32_t *a, uint32_t m, const uint32_t *b, uint32_t n)
 {
     if (METRIC == 0)
-        return m == n ? verify_ham<K>(a, sa, b, sb, m) : K + 1;
+        return m == n ? verify_ham<K>(a, b, m) : K + 1;
     if (K == 1)
-        return verify_lev1(a, sa, m, b, sb, n);
-    return verify_lev_band<K>(a, sa, m, b, sb, n);
+        return verify_lev1(a, m, b, n);
+    return verify_lev_band<K>(a, m, b, n);
 }
 
 // Wave-uniform, read-only data (work list, query keys) is read through the
@@ -375,8 +408,8 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     uint32_t d = K + 1;
     if (act) {
         d = a.survivors_only ? 0u
-                             : verify<METRIC, K>(a.q.str + it.qslot + tq * it.qsw, it.qsw, it.m,
-                                                 a.d.str + it.dslot + te * it.dsw, it.dsw, it.L);
+                             : verify<METRIC, K>(a.q.str + it.qslot + tq * it.qsw, it.m,
+                                                 a.d.str + it.dslot + te * it.dsw, it.L);
     }
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);
@@ -554,8 +587,7 @@ __global__ void k_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
     if (i >= n)
         return;
     const uint32_t qi = qinv[pairs[2 * i]], wi = dinv[pairs[2 * i + 1]];
-    const uint32_t lq = q.len[qi], lw = d.len[wi];
-    dist[i] = verify<METRIC, K>(q.str + q.soff[qi], slot_dwords(lq), lq, d.str + d.soff[wi], slot_dwords(lw), lw);
+    dist[i] = verify<METRIC, K>(q.str + q.soff[qi], q.len[qi], d.str + d.soff[wi], d.len[wi]);
 }
 
 template <int KIND, int METRIC, int K>

@@ -243,3 +243,72 @@ def test_deterministic_repeats(fpm, small):
     first = fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1))
     for _ in range(3):
         assert np.array_equal(fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1)), first)
+
+
+# ------------------------------------------------------- URL-like and mixed
+
+@pytest.fixture(scope="module")
+def url_small():
+    """4,000 URL-like strings x 300 queries, 30% near-matches with 1 or 2 edits."""
+    return datagen.url_workload(4000, 300, 5, 0.3, (1, 2))
+
+
+@pytest.fixture(scope="module")
+def mixed_small():
+    """2,000 English-like + 2,000 URL-like strings x 300 mixed queries."""
+    return datagen.mixed_workload(2000, 2000, 300, 9)
+
+
+URL_CASES = [
+    (oracle.OCC, 32, oracle.LEV, 1), (oracle.OCC, 32, oracle.LEV, 2), (oracle.COUNT, 32, oracle.LEV, 1),
+    (oracle.COUNT, 32, oracle.LEV, 2), (oracle.OCC, 16, oracle.LEV, 2), (oracle.POS, 32, oracle.HAM, 2),
+    (oracle.COUNT, 32, oracle.HAM, 1), (oracle.OCCH, 32, oracle.HAM, 1),
+]
+
+
+@pytest.mark.parametrize("variant,bits,metric,k", URL_CASES)
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("which", ["url", "mixed"])
+def test_long_strings_match_equals_oracle(fpm, url_small, mixed_small, variant, bits, metric, k, schedule, which):
+    d, q = url_small if which == "url" else mixed_small
+    say(which, VARIANT_NAMES[variant], bits, metric, k, schedule)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "mixed" if which == "url" else "common")
+    got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule), with_stats=True)
+    ref = oracle_match(which, d, q, metric, k)
+    assert np.array_equal(got, ref)
+    ex, surv, _ = oracle.filter_stats(d, q, variant, bits, fpm.fpm_get_map(ix), metric, k)
+    assert (st["pairs_examined"], st["survivors"]) == (ex, surv)
+
+
+@pytest.mark.parametrize("name,bits,metric,k", [("url_1m_q10k", 32, oracle.LEV, 2), ("url_1m_q10k", 32, oracle.LEV, 1),
+                                                ("mixed_2m_q64k", 32, oracle.LEV, 1),
+                                                ("english_1m_q10k", 16, oracle.LEV, 1),
+                                                ("english_1m_q10k", 32, oracle.HAM, 1)])
+def test_full_size_sampled_parity(fpm, name, bits, metric, k):
+    """Full-size workloads in the benchmark's launch configuration (batched,
+    persistent, hipGraph): the rows of 48 sampled queries equal the oracle's
+    (length-pruned mode, exact since Lev >= |m - n|), and the filtered result
+    equals the GPU brute force on every query."""
+    import torch
+
+    d, q = datagen.workload(name)
+    nq = q[1].size - 1
+    say("full size", name, bits, metric, k)
+    ix = fpm.fpm_build_fingerprints(d, "occ", bits, "common")
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()  # the plans run on their own streams
+    res = {}
+    for sched in (fpm.FPM_SCHED_BATCHED, fpm.FPM_SCHED_BRUTE):
+        plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), metric, k, fpm.options(schedule=sched))
+        fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+        res[sched] = fpm.fpm_plan_copy_matches(plan)
+        del plan
+    assert np.array_equal(res[fpm.FPM_SCHED_BATCHED], res[fpm.FPM_SCHED_BRUTE])
+    sample = np.random.default_rng(11).choice(nq, 48, replace=False)
+    sample.sort()
+    ref = oracle.match(d, datagen.take_csr(q, sample), metric, k, length_pruned=True)
+    ref[:, 0] = sample[ref[:, 0]]
+    got = res[fpm.FPM_SCHED_BATCHED]
+    got = got[np.isin(got[:, 0], sample)]
+    assert np.array_equal(got, ref)

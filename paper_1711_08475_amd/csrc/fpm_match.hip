@@ -13,10 +13,12 @@
 //   t   = popcount(kq ^ kw) - (2k + 1)   one v_xor, one v_bcnt with accumulator
 //   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
 // i.e. three vector instructions per (query, word) pair.  The lane's 16-bit
-// survivor mask is then appended to a per-wave queue in LDS (prefix sum of
-// the per-lane counts over the wave from five ballots); every time the queue
-// holds 64 entries the wave pops 64 and verifies them, one per lane, so the
-// verifier always runs on full waves.  Matches leave through one atomic per
+// survivor mask is then appended to a per-wave queue in LDS: each lane with
+// survivors reserves its range with one LDS atomic add on the wave's queue
+// counter (the LDS unit serialises the lanes, the VALU computes no prefix
+// sum; entry order does not matter).  Every time the queue holds 64 entries
+// the wave pops 64 and verifies them, one per lane, so the verifier always
+// runs on full waves.  Matches leave through one atomic per
 // flush of a per-wave LDS staging buffer.
 //
 // Verifiers (k-bounded, exact below k+1):
@@ -39,9 +41,10 @@ constexpr int kChunk = 16;                // queries per filter pass = survivor-
 constexpr int kQueueCap = 64 * kChunk + 64;  // entries per wave: < 64 left + one full pass
 // Matches are staged per wave in LDS and leave through one atomic per flush;
 // a flush happens once more than kOutFlush are staged, so a drain (<= 64
-// new matches) always fits.  Queue + staging = 5120 bytes per wave, 20 KB
-// per block: eight blocks fill the 160 KB of LDS of a compute unit.
-constexpr int kOutCap = 96;
+// new matches) always fits.  Queue + staging + queue counter = 5116 bytes
+// per wave, at most 20 KB per block: eight blocks fit the 160 KB of LDS of a
+// compute unit.
+constexpr int kOutCap = 95;
 constexpr int kOutFlush = kOutCap - 64;
 
 // -------------------------------------------------------------- filters
@@ -430,6 +433,7 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     using Key = typename F::Key;
     __shared__ uint32_t queue_all[kWaves][kQueueCap];
     __shared__ uint64_t out_all[kWaves][kOutCap];
+    __shared__ uint32_t qcount[kWaves];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     uint32_t *queue = queue_all[wave];
     uint64_t *out = out_all[wave];
@@ -470,22 +474,24 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                     msk = 0;
                 const uint32_t c = (uint32_t)__builtin_popcount(msk);
                 if (__ballot(c != 0)) {
-                    uint32_t pre = 0, tot = 0;
-#pragma unroll
-                    for (int b = 0; b < 5; ++b) {
-                        const uint64_t m = __ballot((c >> b) & 1u);
-                        pre += lanes_below(m) << b;
-                        tot += (uint32_t)__popcll(m) << b;
-                    }
-                    uint32_t pos = qlen + pre;
+                    // queue positions from an LDS atomic per lane (the LDS unit
+                    // hands out the ranges; no VALU prefix sum)
+                    if (lane == 0)
+                        qcount[wave] = qlen;
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t pos = 0;
+                    if (c)
+                        pos = atomicAdd(&qcount[wave], c);
                     const uint32_t ent0 = ((j0 + kChunk - 1) << kWordBits) | (e - it.ds);
                     while (msk) {
                         const uint32_t bit = 31u - (uint32_t)__builtin_clz(msk);
                         queue[pos++] = ent0 - (bit << kWordBits);
                         msk &= ~(1u << bit);
                     }
-                    qlen += tot;
-                    survivors += tot;
+                    __builtin_amdgcn_wave_barrier();
+                    const uint32_t nlen = __builtin_amdgcn_readfirstlane(qcount[wave]);
+                    survivors += nlen - qlen;
+                    qlen = nlen;
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
                 }

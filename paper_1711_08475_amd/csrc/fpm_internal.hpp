@@ -23,7 +23,7 @@ namespace fpm {
 constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
 constexpr int kMaxPairs = 256 * 5;   // (query length, word length) pairs, |dL| <= 2
-constexpr int kRadixBlocks = 256;    // blocks of one stable radix pass
+constexpr int kRadixBlocks = 64;     // blocks of one stable radix pass (16 waves each)
 
 __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 {

@@ -7,10 +7,12 @@
 //   scan:    one block turns the digit-major table [256][kRadixBlocks] into
 //            exclusive offsets, so block b's first item of digit d goes to
 //            offs[d][b];
-//   scatter: each block walks its range in order, one wave, 64 items at a
-//            time; lanes with equal digits are found with 8 ballots, so the
-//            rank of a lane among equal digits is the popcount of its peers
-//            below it -- the pass is stable.
+//   scatter: each block splits its range into kScatterWaves contiguous
+//            sub-ranges, counts their digits in LDS, derives each wave's
+//            starting offsets, and every wave walks its sub-range in order,
+//            64 items at a time; lanes with equal digits are found with 8
+//            ballots, so the rank of a lane among equal digits is the
+//            popcount of its peers below it -- the pass is stable.
 // The item count may live in device memory (match list), so every kernel
 // splits [0, n) into kRadixBlocks ranges at run time.
 #include "fpm_internal.hpp"
@@ -86,24 +88,47 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
     }
 }
 
-// One wave per block.  vals_in == nullptr means value = item index.
+// kScatterWaves waves per block.  vals_in == nullptr means value = item index.
+constexpr int kScatterWaves = 16;
+
 template <typename K>
-__global__ void __launch_bounds__(64) k_radix_scatter(const K *keys_in, const uint32_t *vals_in, K *keys_out,
-                                                      uint32_t *vals_out, const uint64_t *dcount, uint64_t hcount,
-                                                      uint64_t cap, uint32_t shift, const uint32_t *offs)
+__global__ void __launch_bounds__(64 * kScatterWaves) k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
+                                                                      K *keys_out, uint32_t *vals_out,
+                                                                      const uint64_t *dcount, uint64_t hcount,
+                                                                      uint64_t cap, uint32_t shift,
+                                                                      const uint32_t *offs)
 {
-    __shared__ uint32_t running[256];
-    const uint32_t b = blockIdx.x, lane = threadIdx.x;
-    for (uint32_t d = lane; d < 256; d += 64)
-        running[d] = offs[d * kRadixBlocks + b];
+    __shared__ uint32_t run[kScatterWaves][256];
+    const uint32_t b = blockIdx.x, lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    for (uint32_t i = threadIdx.x; i < kScatterWaves * 256; i += blockDim.x)
+        (&run[0][0])[i] = 0;
     __syncthreads();
     const uint64_t n = range_n(dcount, hcount, cap);
-    const uint64_t lo = n * b / kRadixBlocks, hi = n * (b + 1) / kRadixBlocks;
+    const uint64_t blo = n * b / kRadixBlocks, bhi = n * (b + 1) / kRadixBlocks;
+    const uint64_t lo = blo + (bhi - blo) * w / kScatterWaves, hi = blo + (bhi - blo) * (w + 1) / kScatterWaves;
+    // digit counts of each wave's sub-range
+    for (uint64_t i = lo + lane; i < hi; i += 64)
+        atomicAdd(&run[w][(uint32_t)(keys_in[i] >> shift) & 0xFFu], 1u);
+    __syncthreads();
+    // exclusive prefix over the waves, starting at the block's offsets
+    if (threadIdx.x < 256) {
+        const uint32_t d = threadIdx.x;
+        uint32_t r = offs[d * kRadixBlocks + b];
+        for (int ww = 0; ww < kScatterWaves; ++ww) {
+            const uint32_t c = run[ww][d];
+            run[ww][d] = r;
+            r += c;
+        }
+    }
+    __syncthreads();
+    uint32_t *running = run[w];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    K next = (lo + lane < hi) ? keys_in[lo + lane] : K(0);
     for (uint64_t base = lo; base < hi; base += 64) {
         const uint64_t i = base + lane;
         const bool active = i < hi;
-        K key = active ? keys_in[i] : K(0);
+        const K key = next;
+        next = (i + 64 < hi) ? keys_in[i + 64] : K(0);  // prefetch the next group
         uint32_t val = 0;
         if (active)
             val = vals_in ? vals_in[i] : (uint32_t)i;
@@ -115,7 +140,7 @@ __global__ void __launch_bounds__(64) k_radix_scatter(const K *keys_in, const ui
             const uint64_t m = __ballot(set);
             peers &= set ? m : ~m;
         }
-        uint32_t start = running[digit];
+        const uint32_t start = running[digit];
         __builtin_amdgcn_wave_barrier();
         if (active) {
             const uint32_t rank = (uint32_t)__popcll(peers & below);
@@ -128,7 +153,6 @@ __global__ void __launch_bounds__(64) k_radix_scatter(const K *keys_in, const ui
                 running[digit] = start + (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_wave_barrier();
-        __syncthreads();
     }
 }
 
@@ -193,9 +217,10 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, cons
     hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
     static_assert(256 * kRadixBlocks % 4096 == 0, "scan table must split into 1024 runs of 4k entries");
+    // kRadixBlocks = 64: 16 entries per scan thread
     hipLaunchKernelGGL(k_scan_exclusive<256 * kRadixBlocks / 1024>, dim3(1), dim3(1024), 0, s, scratch);
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64), 0, s, kin, vin, kout, vout, dcount, hcount,
-                       cap, shift, scratch);
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
+                       dcount, hcount, cap, shift, scratch);
 }
 
 }  // namespace

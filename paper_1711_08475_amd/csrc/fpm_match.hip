@@ -469,9 +469,12 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                 for (int t = 0; t < kChunk; ++t)
                     msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
                 // bit (kChunk - 1 - t) <-> query j0 + t; drop the padding queries
-                msk &= (0xFFFFu << (kChunk - nqc)) & 0xFFFFu;
-                if (!valid)
-                    msk = 0;
+                // and the lanes past the slab (only on the item's ragged edges)
+                if (nqc < (uint32_t)kChunk || e0 + 64 > it.de) {
+                    msk &= (0xFFFFu << (kChunk - nqc)) & 0xFFFFu;
+                    if (!valid)
+                        msk = 0;
+                }
                 const uint32_t c = (uint32_t)__builtin_popcount(msk);
                 if (__ballot(c != 0)) {
                     // queue positions from an LDS atomic per lane (the LDS unit

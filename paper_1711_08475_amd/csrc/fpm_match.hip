@@ -457,10 +457,12 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     while (item < n_items) {
         const Item it = decode_item(a, item, n_pairs);
         uint32_t qlen = 0;
+        Key wk_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
         for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
             const uint32_t e = e0 + lane;
             const bool valid = e < it.de;
-            const Key wk = valid ? dkeys[e] : Key(0);
+            const Key wk = wk_next;
+            wk_next = (e + 64 < it.de) ? dkeys[e + 64] : Key(0);  // next group's key, loaded ahead
             for (uint32_t j0 = 0; j0 < it.qn; j0 += kChunk) {
                 const uint32_t nqc = min((uint32_t)kChunk, it.qn - j0);
                 const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry kChunk padding entries

@@ -7,6 +7,7 @@
 // one captured hipGraph.
 #include <algorithm>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -145,7 +146,8 @@ void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, 
 
 struct DevCounters {
     uint64_t n_out, survivors, cells, examined;
-    uint32_t err, n_pairs, n_items, counter;
+    uint32_t err, n_pairs, n_items, pad;
+    uint32_t counters[kStripes * kStripeStride];  // persistent work counters
 };
 
 }  // namespace
@@ -204,7 +206,7 @@ struct fpm_plan {
     std::vector<PairRec> h_pairs;
     uint32_t h_hdr[2] = {0, 0};  // host source of an async copy: lives in the plan
 
-    WorkList worklist() { return WorkList{pairs, &ctr->n_pairs, &ctr->n_items, &ctr->counter, &ctr->examined}; }
+    WorkList worklist() { return WorkList{pairs, &ctr->n_pairs, &ctr->n_items, ctr->counters, &ctr->examined}; }
 
     void drop_graphs()
     {
@@ -777,7 +779,7 @@ fpm_status fpm_plan_result(fpm_plan *p, const fpm_hit **d_matches, uint64_t *n_o
     DevCounters c;
     for (int attempt = 0; attempt < 3; ++attempt) {
         HIPCHK(hipStreamSynchronize(p->stream));
-        HIPCHK(hipMemcpy(&c, p->ctr, sizeof(c), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&c, p->ctr, offsetof(DevCounters, counters), hipMemcpyDeviceToHost));
         if (c.err)
             return fail(FPM_EINVAL, "query batch: %s",
                         (c.err & 2) ? "offsets decrease"

@@ -54,11 +54,17 @@ struct PairRec {
     uint32_t qlen, dlen;
 };
 
+// The persistent schedule hands out work items through kStripes counters,
+// kStripeStride words apart (one per cache line): counter s serves items
+// nw + kStripes * v + s after the static first round of nw items.
+constexpr int kStripes = 8;
+constexpr int kStripeStride = 64;
+
 struct WorkList {
     PairRec *pairs;       // [kMaxPairs]
     uint32_t *n_pairs;    // device scalar
     uint32_t *n_items;    // device scalar
-    uint32_t *counter;    // persistent work counter
+    uint32_t *counters;   // [kStripes * kStripeStride], zero before a persistent launch
     uint64_t *examined;   // device scalar: length-compatible pairs
 };
 
@@ -122,7 +128,8 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
                        uint32_t slab, uint32_t order, PairRec *pairs, uint32_t *n_pairs, uint64_t *examined);
 
 // Launch the fused filter -> LDS queue -> verify kernel.
-//   persistent: grid = persistent_blocks, items from the atomic counter;
+//   persistent: grid = persistent_blocks; wave w takes item w first, then
+//   items from the striped counters;
 //   otherwise grid covers host_items items, one per wave.
 hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s);

@@ -7,6 +7,10 @@
 // |L - m| <= k (Levenshtein >= |L - m|).  Each compatible pair of buckets is
 // cut into work items: a tile of up to `qtile` queries of length m times a
 // slab of up to `slab` words of length L.  A work item belongs to one wave.
+// The persistent launch gives wave w item w first, then hands out the rest
+// through eight striped atomic counters (no single contended address, no
+// burst of atomics at start-up), and each wave's issue priority follows its
+// item's position in the list so that items finish about in list order.
 //
 // Per work item, per 64 dictionary words (one per lane) and per 16 queries
 // (their filter keys are wave-uniform, so they sit in scalar registers):
@@ -426,6 +430,48 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     }
 }
 
+// ------------------------------------------------------------ schedule
+
+// Issue priority follows the item's position in the work list, so items
+// finish roughly in the order they were taken: the hardware otherwise
+// favours the oldest waves, and an item held by a young wave can run for
+// most of the launch and set its tail.
+__device__ __forceinline__ void set_priority(uint32_t item, uint32_t n_items)
+{
+    const uint32_t lvl = (uint32_t)(((uint64_t)item * 4u) / n_items);
+    if (lvl == 0)
+        __builtin_amdgcn_s_setprio(3);
+    else if (lvl == 1)
+        __builtin_amdgcn_s_setprio(2);
+    else if (lvl == 2)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
+// Next item of the persistent schedule.  After the static first round of
+// nw items, counter s hands out items nw + kStripes * v + s; a wave starts
+// on the counter of its block's stripe and moves on to the next stripe once
+// one is exhausted, so a few waves do not wait behind one contended atomic
+// and no stripe is left with work.  Returns n_items when every stripe is
+// exhausted (each wave then has seen all kStripes counters once).
+__device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, uint32_t n_items, uint32_t &stripe,
+                                              uint32_t &tries, uint32_t lane)
+{
+    while (tries < (uint32_t)kStripes) {
+        uint32_t v = 0;
+        if (lane == 0)
+            v = atomicAdd(&counters[stripe * kStripeStride], 1u);
+        v = __builtin_amdgcn_readfirstlane(v);
+        const uint64_t cand = (uint64_t)nw + (uint64_t)kStripes * v + stripe;
+        if (cand < n_items)
+            return (uint32_t)cand;
+        stripe = (stripe + 1) % kStripes;
+        ++tries;
+    }
+    return n_items;
+}
+
 template <int KIND, int METRIC, int K, bool PERSISTENT>
 __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 {
@@ -445,16 +491,13 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     const uint32_t n_pairs = *as_const(a.wl.n_pairs);
     uint64_t survivors = 0, cells = 0;
 
-    uint32_t item;
-    if (PERSISTENT) {
-        uint32_t v = 0;
-        if (lane == 0)
-            v = atomicAdd(a.wl.counter, 1u);
-        item = __builtin_amdgcn_readfirstlane(v);
-    } else {
-        item = blockIdx.x * kWaves + wave;
-    }
+    // first item: the global wave index (no atomics at start-up); `wave`
+    // itself stays a vector value, the item is made uniform explicitly
+    const uint32_t nw = gridDim.x * kWaves;
+    uint32_t stripe = blockIdx.x % kStripes, tries = 0;
+    uint32_t item = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
     while (item < n_items) {
+        set_priority(item, n_items);
         const Item it = decode_item(a, item, n_pairs);
         uint32_t qlen = 0;
         Key wk_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
@@ -506,11 +549,9 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
             drain<METRIC, K>(a, it, queue, qlen, qlen, lane, cells, out, ocount);
         if (!PERSISTENT)
             break;
-        uint32_t v = 0;
-        if (lane == 0)
-            v = atomicAdd(a.wl.counter, 1u);
-        item = __builtin_amdgcn_readfirstlane(v);
+        item = next_item(a.wl.counters, nw, n_items, stripe, tries, lane);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (ocount)
         flush(a, out, ocount, lane);
     if (lane == 0) {
@@ -586,7 +627,6 @@ __global__ void __launch_bounds__(256) k_worklist(const uint32_t *qoff, const ui
         *wl.n_pairs = s_pairs[255];
         *wl.n_items = s_items[255];
         *wl.examined = s_exam[255];
-        *wl.counter = 0;
     }
 }
 

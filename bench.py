@@ -90,7 +90,8 @@ def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k
     t = time.perf_counter()
     best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2)
     log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s")
-    entry = {k: v for k, v in best.as_dict().items() if k in ("schedule", "queries_per_item", "slab", "bucket_order")}
+    entry = {k: v for k, v in best.as_dict().items()
+             if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split")}
     table[key] = entry
     with open(TUNING_FILE, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)

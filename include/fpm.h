@@ -110,7 +110,11 @@ typedef struct {
     uint32_t time_kernel;      /* 1: bracket the match kernel of every run with HIP events (see
                                   fpm_plan_kernel_ms); a batched graph is then split into a prep graph
                                   and a post graph around a direct launch of the match kernel */
-    uint32_t reserved[8];
+    uint32_t tail_split;       /* batched and brute: percent (1..99) of each bucket pair's words that go
+                                  into tail items of a smaller tile (queries_per_item / 2 by slab / 4,
+                                  at least 16 by 64), listed after every full-size item so that a launch
+                                  ends on short items; 0 = default (100: no tail items) */
+    uint32_t reserved[7];
 } fpm_options;
 
 typedef struct fpm_index fpm_index;
@@ -223,10 +227,12 @@ void fpm_plan_destroy(fpm_plan *plan);
 
 /* Autotuner for the batched schedule: times every combination of
  * queries_per_item in {16, 32, 64, 128, 256}, slab in {512, 1024, 2048,
- * 4096, 8192, 16384} and both bucket orders on the given device queries, and
- * writes the fastest into *best (its schedule = FPM_SCHED_BATCHED).
- * `timings_out` (nullable) receives up to `max_timings` rows of
- * (queries_per_item, slab, bucket_order, ms) as floats. */
+ * 4096, 8192, 16384} and both bucket orders on the given device queries with
+ * the tail split of *best (on entry), then the fastest of those with tail
+ * splits 10, 25 and 40 (100 = none), and writes the fastest overall into *best
+ * (its schedule = FPM_SCHED_BATCHED).  `timings_out` (nullable) receives up
+ * to `max_timings` rows of (queries_per_item, slab, bucket_order,
+ * tail_split, ms) as floats. */
 fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t n_queries,
                         uint64_t query_bytes, fpm_metric metric, uint32_t k, uint32_t repeats, fpm_options *best,
                         float *timings_out, uint32_t max_timings, uint32_t *n_timings);

@@ -500,6 +500,10 @@ static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
         return fail(FPM_EINVAL, "waves_per_cu must be <= 64");
     if (o->time_kernel > 1)
         return fail(FPM_EINVAL, "time_kernel must be 0 or 1");
+    if (!o->tail_split)
+        o->tail_split = 100;
+    if (o->tail_split > 100)
+        return fail(FPM_EINVAL, "tail_split must be in 1..100 (0 = default)");
     return FPM_OK;
 }
 
@@ -606,7 +610,7 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
         HIPCHK(hipMemcpyAsync(&p->ctr->examined, &p->host_examined, sizeof(uint64_t), hipMemcpyHostToDevice, s));
     } else {
         launch_worklist(p->q.off, ix->words.off, p->metric, p->k, p->opt.queries_per_item, p->opt.slab,
-                        p->opt.bucket_order, p->worklist(), s);
+                        p->opt.bucket_order, p->opt.tail_split >= 100 ? 0u : p->opt.tail_split, p->worklist(), s);
     }
     return FPM_OK;
 }
@@ -621,8 +625,6 @@ static fpm_status enqueue_kernel(fpm_plan *p, bool plain)
     a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells};
     a.out_keys = p->keys;
     a.out_cap = p->cap;
-    a.qtile = p->opt.queries_per_item;
-    a.slab = p->opt.slab;
     a.wbits = ix->wbits;
     a.survivors_only = p->survivors_only ? 1u : 0u;
     hipError_t e =
@@ -1008,53 +1010,72 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
         return fail(FPM_EINVAL, "null pointer");
     static const uint32_t qts[] = {16, 32, 64, 128, 256};
     static const uint32_t slabs[] = {512, 1024, 2048, 4096, 8192, 16384};
+    static const uint32_t tails[] = {10, 25, 40};
     if (repeats == 0)
         repeats = 3;
     fpm_options base = *best;
+    if (!base.tail_split)
+        base.tail_split = 100;
     float best_ms = 1e30f;
     uint32_t nt = 0;
+    // time one configuration; the fastest so far goes to *best
+    auto trial = [&](fpm_options o) -> fpm_status {
+        o.schedule = FPM_SCHED_BATCHED;
+        if (!o.use_graph)
+            o.use_graph = 1;
+        fpm_plan *p = nullptr;
+        fpm_status st = plan_create(ix, n_queries, query_bytes, metric, k, &o, nullptr, false, &p);
+        if (st)
+            return st;
+        float tot = 0.f;
+        for (uint32_t r = 0; r <= repeats && !st; ++r) {
+            st = fpm_plan_run(p, d_qbytes, d_qoffsets, n_queries);
+            fpm_stats s;
+            if (!st)
+                st = fpm_plan_result(p, nullptr, nullptr, &s);
+            if (!st && r > 0)
+                tot += s.ms;
+        }
+        if (!st)
+            o.match_capacity = (uint32_t)std::min<uint64_t>(p->cap, 0xFFFFFFFFu);
+        plan_free(p);
+        if (st)
+            return st;
+        const float ms = tot / repeats;
+        if (timings_out && nt < max_timings) {
+            timings_out[5 * nt + 0] = (float)o.queries_per_item;
+            timings_out[5 * nt + 1] = (float)o.slab;
+            timings_out[5 * nt + 2] = (float)o.bucket_order;
+            timings_out[5 * nt + 3] = (float)o.tail_split;
+            timings_out[5 * nt + 4] = ms;
+        }
+        ++nt;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = o;
+        }
+        return FPM_OK;
+    };
     for (uint32_t order = 0; order < 2; ++order) {
         for (uint32_t qt : qts) {
             for (uint32_t sl : slabs) {
                 fpm_options o = base;
-                o.schedule = FPM_SCHED_BATCHED;
                 o.queries_per_item = qt;
                 o.slab = sl;
                 o.bucket_order = order;
-                if (!o.use_graph)
-                    o.use_graph = 1;
-                fpm_plan *p = nullptr;
-                fpm_status st = plan_create(ix, n_queries, query_bytes, metric, k, &o, nullptr, false, &p);
-                if (st)
+                if (fpm_status st = trial(o))
                     return st;
-                float tot = 0.f;
-                for (uint32_t r = 0; r <= repeats && !st; ++r) {
-                    st = fpm_plan_run(p, d_qbytes, d_qoffsets, n_queries);
-                    fpm_stats s;
-                    if (!st)
-                        st = fpm_plan_result(p, nullptr, nullptr, &s);
-                    if (!st && r > 0)
-                        tot += s.ms;
-                }
-                if (!st)
-                    o.match_capacity = (uint32_t)std::min<uint64_t>(p->cap, 0xFFFFFFFFu);
-                plan_free(p);
-                if (st)
-                    return st;
-                const float ms = tot / repeats;
-                if (timings_out && nt < max_timings) {
-                    timings_out[4 * nt + 0] = (float)qt;
-                    timings_out[4 * nt + 1] = (float)sl;
-                    timings_out[4 * nt + 2] = (float)order;
-                    timings_out[4 * nt + 3] = ms;
-                }
-                ++nt;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    *best = o;
-                }
             }
         }
+    }
+    const fpm_options grid_best = *best;
+    for (uint32_t tl : tails) {
+        if (tl == grid_best.tail_split)
+            continue;
+        fpm_options o = grid_best;
+        o.tail_split = tl;
+        if (fpm_status st = trial(o))
+            return st;
     }
     if (n_timings)
         *n_timings = std::min(nt, max_timings);

@@ -22,7 +22,7 @@ namespace fpm {
 
 constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
-constexpr int kMaxPairs = 256 * 5;   // (query length, word length) pairs, |dL| <= 2
+constexpr int kMaxPairs = 2 * 256 * 5;  // (query length, word length) pairs, |dL| <= 2, full + tail part
 constexpr int kRadixBlocks = 64;     // blocks of one stable radix pass (16 waves each)
 
 __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
@@ -52,6 +52,7 @@ struct PairRec {
     uint32_t dbase, nd;  // sorted dictionary range
     uint32_t tiles_d;    // dictionary slabs per query tile
     uint32_t qlen, dlen;
+    uint32_t qtile, slab;  // tile of this record's items
 };
 
 // The persistent schedule hands out work items through kStripes counters,
@@ -80,8 +81,6 @@ struct MatchArgs {
     MatchCounters ctr;
     uint64_t *out_keys;   // packed (query, word, dist) keys
     uint64_t out_cap;
-    uint32_t qtile;       // queries per work item
-    uint32_t slab;        // words per work item
     uint32_t wbits;       // bits of a word index in the packed key
     uint32_t survivors_only;  // 1: report every survivor with dist 0, no verification
 };
@@ -121,8 +120,12 @@ void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_
 void launch_zero(void *p, size_t n_u32, hipStream_t s);
 
 // ----------------------------------------------------------------- match
+// Device work list: for every compatible bucket pair a full-size record
+// (whole slabs covering about (100 - tail_pct)% of its words) and a tail
+// record of (qtile / 2) x (slab / 4) tiles for the rest; all full records
+// come first.  tail_pct = 0: full records only.
 void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
-                     uint32_t slab, uint32_t order, WorkList wl, hipStream_t s);
+                     uint32_t slab, uint32_t order, uint32_t tail_pct, WorkList wl, hipStream_t s);
 // host-side twin used by the plain schedule
 uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
                        uint32_t slab, uint32_t order, PairRec *pairs, uint32_t *n_pairs, uint64_t *examined);

@@ -362,13 +362,14 @@ __device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, u
     }
     const uint32_t base = pairs[lo].item_base, qbase = pairs[lo].qbase, nq = pairs[lo].nq;
     const uint32_t dbase = pairs[lo].dbase, nd = pairs[lo].nd, tiles_d = pairs[lo].tiles_d;
+    const uint32_t qtile = pairs[lo].qtile, slab = pairs[lo].slab;
     const uint32_t t = item - base;
     const uint32_t tq = t / tiles_d, td = t - tq * tiles_d;
     Item it;
-    it.qs = qbase + tq * a.qtile;
-    it.qn = min(a.qtile, qbase + nq - it.qs);
-    it.ds = dbase + td * a.slab;
-    it.de = min(it.ds + a.slab, dbase + nd);
+    it.qs = qbase + tq * qtile;
+    it.qn = min(qtile, qbase + nq - it.qs);
+    it.ds = dbase + td * slab;
+    it.de = min(it.ds + slab, dbase + nd);
     it.m = pairs[lo].qlen;
     it.L = pairs[lo].dlen;
     it.qslot = as_const(a.q.soff)[it.qs];
@@ -453,12 +454,20 @@ __device__ __forceinline__ void set_priority(uint32_t item, uint32_t n_items)
 // nw items, counter s hands out items nw + kStripes * v + s; a wave starts
 // on the counter of its block's stripe and moves on to the next stripe once
 // one is exhausted, so a few waves do not wait behind one contended atomic
-// and no stripe is left with work.  Returns n_items when every stripe is
-// exhausted (each wave then has seen all kStripes counters once).
+// and no stripe is left with work.  `done` (LDS) marks the stripes a wave of
+// the block found exhausted, so the end of a launch costs about one failed
+// atomic per stripe and block instead of one per stripe and wave.  Returns
+// n_items when every stripe is exhausted.
 __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, uint32_t n_items, uint32_t &stripe,
-                                              uint32_t &tries, uint32_t lane)
+                                              uint32_t &tries, uint32_t lane, uint32_t *done)
 {
     while (tries < (uint32_t)kStripes) {
+        // a stripe another wave of this block found exhausted costs no atomic
+        if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & (1u << stripe)) {
+            stripe = (stripe + 1) % kStripes;
+            ++tries;
+            continue;
+        }
         uint32_t v = 0;
         if (lane == 0)
             v = atomicAdd(&counters[stripe * kStripeStride], 1u);
@@ -466,6 +475,8 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, u
         const uint64_t cand = (uint64_t)nw + (uint64_t)kStripes * v + stripe;
         if (cand < n_items)
             return (uint32_t)cand;
+        if (lane == 0)
+            __hip_atomic_fetch_or(done, 1u << stripe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         stripe = (stripe + 1) % kStripes;
         ++tries;
     }
@@ -477,9 +488,13 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 {
     using F = Filter<KIND>;
     using Key = typename F::Key;
-    __shared__ uint32_t queue_all[kWaves][kQueueCap];
+    __shared__ __attribute__((aligned(16))) uint32_t queue_all[kWaves][kQueueCap];
     __shared__ uint64_t out_all[kWaves][kOutCap];
     __shared__ uint32_t qcount[kWaves];
+    __shared__ uint32_t s_done;  // stripes found exhausted
+    if (threadIdx.x == 0)
+        s_done = 0;
+    __syncthreads();
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     uint32_t *queue = queue_all[wave];
     uint64_t *out = out_all[wave];
@@ -549,33 +564,109 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
             drain<METRIC, K>(a, it, queue, qlen, qlen, lane, cells, out, ocount);
         if (!PERSISTENT)
             break;
-        item = next_item(a.wl.counters, nw, n_items, stripe, tries, lane);
+        item = next_item(a.wl.counters, nw, n_items, stripe, tries, lane, &s_done);
     }
     __builtin_amdgcn_s_setprio(0);
-    if (ocount)
-        flush(a, out, ocount, lane);
+    // Block epilogue: one atomic per counter and block (the waves' last
+    // atomics would otherwise all land in the launch's tail, on three
+    // addresses, and slow the items still running).  The queues are empty
+    // now and hold the per-wave sums.
+    __syncthreads();
+    uint64_t *red = (uint64_t *)&queue_all[0][0];
     if (lane == 0) {
-        if (survivors)
-            atomicAdd((unsigned long long *)a.ctr.survivors, (unsigned long long)survivors);
-        if (cells)
-            atomicAdd((unsigned long long *)a.ctr.verify_cells, (unsigned long long)cells);
+        red[3 * wave] = survivors;
+        red[3 * wave + 1] = cells;
+        red[3 * wave + 2] = ocount;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t sv = 0, ce = 0, o = 0, cnt[kWaves];
+        for (int w = 0; w < kWaves; ++w) {
+            sv += red[3 * w];
+            ce += red[3 * w + 1];
+            cnt[w] = red[3 * w + 2];
+        }
+        for (int w = 0; w < kWaves; ++w) {
+            red[3 * w + 2] = o;  // exclusive prefix: the wave's first output slot
+            o += cnt[w];
+        }
+        unsigned long long base = 0;
+        if (o)
+            base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)o);
+        if (sv)
+            atomicAdd((unsigned long long *)a.ctr.survivors, (unsigned long long)sv);
+        if (ce)
+            atomicAdd((unsigned long long *)a.ctr.verify_cells, (unsigned long long)ce);
+        red[3 * kWaves] = base;
+    }
+    __syncthreads();
+    const uint64_t base = red[3 * kWaves] + red[3 * wave + 2];
+    for (uint32_t i = lane; i < ocount; i += 64) {
+        if (base + i < a.out_cap)
+            a.out_keys[base + i] = out[i];
     }
 }
 
 // --------------------------------------------------------- work list
 
-// One block: thread t owns query length m (descending or ascending order)
-// and its up to 2k+1 compatible word lengths.
-__global__ void __launch_bounds__(256) k_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k,
-                                                  uint32_t qtile, uint32_t slab, uint32_t order, WorkList wl)
+// Split of one compatible bucket pair (nq queries, nd words) into a
+// full-size part (whole slabs, about (100 - tail_pct)% of the words) and a
+// tail part of smaller tiles.
+struct PairSplit {
+    uint32_t nd_full, items_full, items_tail;
+};
+
+__host__ __device__ __forceinline__ uint32_t tail_qtile(uint32_t qtile) { return max(16u, (qtile / 2) & ~15u); }
+__host__ __device__ __forceinline__ uint32_t tail_slab(uint32_t slab) { return max(64u, (slab / 4) & ~63u); }
+
+__host__ __device__ __forceinline__ PairSplit split_pair(uint32_t nq, uint32_t nd, uint32_t qtile, uint32_t slab,
+                                                        uint32_t tail_pct)
 {
-    __shared__ uint32_t s_pairs[256], s_items[256];
+    PairSplit r;
+    if (tail_pct == 0) {
+        r.nd_full = nd;
+    } else {
+        const uint32_t keep = nd - (uint32_t)((uint64_t)nd * tail_pct / 100);
+        r.nd_full = keep / slab * slab;
+    }
+    const uint32_t nd_tail = nd - r.nd_full;
+    r.items_full = r.nd_full ? ((nq + qtile - 1) / qtile) * ((r.nd_full + slab - 1) / slab) : 0;
+    const uint32_t qt = tail_qtile(qtile), sl = tail_slab(slab);
+    r.items_tail = nd_tail ? ((nq + qt - 1) / qt) * ((nd_tail + sl - 1) / sl) : 0;
+    return r;
+}
+
+__host__ __device__ __forceinline__ PairRec make_rec(uint32_t item_base, uint32_t qbase, uint32_t nq, uint32_t dbase,
+                                                    uint32_t nd, uint32_t qtile, uint32_t slab, uint32_t m, uint32_t L)
+{
+    PairRec P;
+    P.item_base = item_base;
+    P.qbase = qbase;
+    P.nq = nq;
+    P.dbase = dbase;
+    P.nd = nd;
+    P.tiles_d = (nd + slab - 1) / slab;
+    P.qlen = m;
+    P.dlen = L;
+    P.qtile = qtile;
+    P.slab = slab;
+    return P;
+}
+
+// One block: thread t owns query length m (descending or ascending order)
+// and its up to 2k+1 compatible word lengths.  Four scans over the threads
+// place the full records (and their items) before every tail record.
+__global__ void __launch_bounds__(256) k_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k,
+                                                  uint32_t qtile, uint32_t slab, uint32_t order, uint32_t tail_pct,
+                                                  WorkList wl)
+{
+    __shared__ uint32_t s_cnt[4][256];  // full records, full items, tail records, tail items
     __shared__ unsigned long long s_exam[256];
     const uint32_t t = threadIdx.x;
     const int m = order == 0 ? 255 - (int)t : (int)t;
     const uint32_t nq = qoff[m + 1] - qoff[m];
     const int r = metric == 0 ? 0 : (int)k;
-    uint32_t np = 0, ni = 0;
+    uint32_t c[4] = {0, 0, 0, 0};
     unsigned long long ex = 0;
     if (nq) {
         for (int L = m - r; L <= m + r; ++L) {
@@ -584,48 +675,55 @@ __global__ void __launch_bounds__(256) k_worklist(const uint32_t *qoff, const ui
             const uint32_t nd = doff[L + 1] - doff[L];
             if (!nd)
                 continue;
-            np++;
-            ni += ((nq + qtile - 1) / qtile) * ((nd + slab - 1) / slab);
+            const PairSplit sp = split_pair(nq, nd, qtile, slab, tail_pct);
+            c[0] += sp.items_full ? 1 : 0;
+            c[1] += sp.items_full;
+            c[2] += sp.items_tail ? 1 : 0;
+            c[3] += sp.items_tail;
             ex += (unsigned long long)nq * nd;
         }
     }
-    s_pairs[t] = np;
-    s_items[t] = ni;
+    for (int v = 0; v < 4; ++v)
+        s_cnt[v][t] = c[v];
     s_exam[t] = ex;
     __syncthreads();
     for (uint32_t o = 1; o < 256; o <<= 1) {
-        const uint32_t a = t >= o ? s_pairs[t - o] : 0, b = t >= o ? s_items[t - o] : 0;
-        const unsigned long long c = t >= o ? s_exam[t - o] : 0;
+        uint32_t add[4];
+        for (int v = 0; v < 4; ++v)
+            add[v] = t >= o ? s_cnt[v][t - o] : 0;
+        const unsigned long long e = t >= o ? s_exam[t - o] : 0;
         __syncthreads();
-        s_pairs[t] += a;
-        s_items[t] += b;
-        s_exam[t] += c;
+        for (int v = 0; v < 4; ++v)
+            s_cnt[v][t] += add[v];
+        s_exam[t] += e;
         __syncthreads();
     }
-    uint32_t pidx = s_pairs[t] - np, ibase = s_items[t] - ni;
+    const uint32_t full_pairs = s_cnt[0][255], full_items = s_cnt[1][255];
+    uint32_t pf = s_cnt[0][t] - c[0], ifull = s_cnt[1][t] - c[1];
+    uint32_t pt = full_pairs + s_cnt[2][t] - c[2], itail = full_items + s_cnt[3][t] - c[3];
     if (nq) {
+        const uint32_t qt2 = tail_qtile(qtile), sl2 = tail_slab(slab);
         for (int L = m - r; L <= m + r; ++L) {
             if (L < 0 || L > 255)
                 continue;
             const uint32_t nd = doff[L + 1] - doff[L];
             if (!nd)
                 continue;
-            PairRec P;
-            P.item_base = ibase;
-            P.qbase = qoff[m];
-            P.nq = nq;
-            P.dbase = doff[L];
-            P.nd = nd;
-            P.tiles_d = (nd + slab - 1) / slab;
-            P.qlen = (uint32_t)m;
-            P.dlen = (uint32_t)L;
-            wl.pairs[pidx++] = P;
-            ibase += ((nq + qtile - 1) / qtile) * P.tiles_d;
+            const PairSplit sp = split_pair(nq, nd, qtile, slab, tail_pct);
+            if (sp.items_full) {
+                wl.pairs[pf++] = make_rec(ifull, qoff[m], nq, doff[L], sp.nd_full, qtile, slab, (uint32_t)m, (uint32_t)L);
+                ifull += sp.items_full;
+            }
+            if (sp.items_tail) {
+                wl.pairs[pt++] = make_rec(itail, qoff[m], nq, doff[L] + sp.nd_full, nd - sp.nd_full, qt2, sl2,
+                                          (uint32_t)m, (uint32_t)L);
+                itail += sp.items_tail;
+            }
         }
     }
     if (t == 255) {
-        *wl.n_pairs = s_pairs[255];
-        *wl.n_items = s_items[255];
+        *wl.n_pairs = full_pairs + s_cnt[2][255];
+        *wl.n_items = full_items + s_cnt[3][255];
         *wl.examined = s_exam[255];
     }
 }
@@ -688,16 +786,9 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
             const uint32_t nd = doff[L + 1] - doff[L];
             if (!nd)
                 continue;
-            PairRec &P = pairs[np++];
-            P.item_base = items;
-            P.qbase = qoff[m];
-            P.nq = nq;
-            P.dbase = doff[L];
-            P.nd = nd;
-            P.tiles_d = (nd + slab - 1) / slab;
-            P.qlen = (uint32_t)m;
-            P.dlen = (uint32_t)L;
-            items += ((nq + qtile - 1) / qtile) * P.tiles_d;
+            pairs[np] = make_rec(items, qoff[m], nq, doff[L], nd, qtile, slab, (uint32_t)m, (uint32_t)L);
+            items += ((nq + qtile - 1) / qtile) * pairs[np].tiles_d;
+            ++np;
             ex += (uint64_t)nq * nd;
         }
     }
@@ -707,9 +798,9 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
 }
 
 void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uint32_t k, uint32_t qtile,
-                     uint32_t slab, uint32_t order, WorkList wl, hipStream_t s)
+                     uint32_t slab, uint32_t order, uint32_t tail_pct, WorkList wl, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(256), 0, s, qoff, doff, metric, k, qtile, slab, order, wl);
+    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(256), 0, s, qoff, doff, metric, k, qtile, slab, order, tail_pct, wl);
 }
 
 hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,

@@ -63,7 +63,7 @@ class Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("queries_per_item", ctypes.c_uint32), ("slab", ctypes.c_uint32),
                 ("bucket_order", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 8)]
+                ("tail_split", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -88,7 +88,10 @@ class LearnReport(ctypes.Structure):
 
 def options(**kw) -> Options:
     o = Options()
+    names = {f for f, _ in Options._fields_ if f != "reserved"}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r}")
         setattr(o, k, v)
     return o
 
@@ -341,11 +344,11 @@ def fpm_plan_kernel_ms(plan: Plan, max_runs: int = 256) -> np.ndarray:
 def fpm_autotune(ix: Index, d_qbytes: int, d_qoffsets: int, n_queries: int, query_bytes: int, metric="lev",
                  k: int = 1, repeats: int = 3, base: Options | None = None):
     best = base if base is not None else Options()
-    tim = (ctypes.c_float * (4 * 128))()
+    tim = (ctypes.c_float * (5 * 128))()
     nt = ctypes.c_uint32()
     _check(lib().fpm_autotune(ix.handle, vp(d_qbytes), vp(d_qoffsets), n_queries, query_bytes,
                               _code(METRICS, metric), k, repeats, ctypes.byref(best), tim, 128, ctypes.byref(nt)))
-    rows = [tuple(tim[4 * i:4 * i + 4]) for i in range(nt.value)]
+    rows = [tuple(tim[5 * i:5 * i + 5]) for i in range(nt.value)]
     return best, rows
 
 

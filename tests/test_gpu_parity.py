@@ -192,11 +192,12 @@ def test_everything_survives_and_ragged_buckets(fpm):
     none = np.full(256, 255, dtype=np.uint8)
     for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
         ref = oracle.match(d, q, metric, k)
-        for sched, qt, slab in [(0, 16, 64), (1, 32, 128), (1, 1024, 1 << 20), (0, 64, 16384)]:
-            say("all survive", metric, k, sched, qt, slab)
+        for sched, qt, slab, tail in [(0, 16, 64, 0), (1, 32, 128, 0), (1, 1024, 1 << 20, 0), (0, 64, 16384, 0),
+                                      (1, 16, 64, 99), (1, 64, 256, 50), (1, 32, 128, 100)]:
+            say("all survive", metric, k, sched, qt, slab, tail)
             ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=none)
-            got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched, queries_per_item=qt, slab=slab),
-                                    with_stats=True)
+            got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched, queries_per_item=qt, slab=slab,
+                                                                  tail_split=tail), with_stats=True)
             assert np.array_equal(got, ref)
             assert st["survivors"] == st["pairs_examined"]
 
@@ -234,6 +235,46 @@ def test_errors(fpm, small):
     with pytest.raises(fpm.FpmError) as e:
         fpm.fpm_match(ix, q, "lev", 1, fpm.options(queries_per_item=24))
     assert e.value.status == fpm.FPM_EINVAL
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1, tail_split=101))
+    assert e.value.status == fpm.FPM_EINVAL
+
+
+def expected_items(d, q, metric, k, qt, slab, tail):
+    """Work items of the batched schedule's list: per compatible bucket pair,
+    whole slabs covering about (100 - tail)% of the words in full tiles and
+    the rest in (qt / 2) x (slab / 4) tiles (tail = 100: full tiles only)."""
+    cd = np.bincount(datagen.csr_lengths(d), minlength=260)
+    cq = np.bincount(datagen.csr_lengths(q), minlength=260)
+    r = 0 if metric == "ham" else k
+    qt2, sl2 = max(16, (qt // 2) & ~15), max(64, (slab // 4) & ~63)
+    ceil = lambda a, b: -(-a // b)
+    items = 0
+    for m in range(256):
+        for L in range(max(m - r, 0), min(m + r, 255) + 1):
+            nq, nd = int(cq[m]), int(cd[L])
+            if not nq or not nd:
+                continue
+            full = nd if tail == 100 else (nd - nd * tail // 100) // slab * slab
+            items += (ceil(nq, qt) * ceil(full, slab) if full else 0)
+            items += (ceil(nq, qt2) * ceil(nd - full, sl2) if nd - full else 0)
+    return items
+
+
+@pytest.mark.parametrize("tail", [1, 10, 25, 40, 99, 100])
+def test_tail_split(fpm, small, tail):
+    """The split of each bucket pair into full-size and tail items covers
+    every pair once: the match list equals the oracle's whatever the split,
+    and the item count is the documented one."""
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    for metric, k, qt, slab in [("lev", 1, 32, 256), ("lev", 2, 64, 1024), ("ham", 1, 16, 64)]:
+        say("tail split", tail, metric, k, qt, slab)
+        got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=fpm.FPM_SCHED_BATCHED, queries_per_item=qt,
+                                                              slab=slab, tail_split=tail), with_stats=True)
+        ref = oracle_match("small", d, q, oracle.LEV if metric == "lev" else oracle.HAM, k)
+        assert np.array_equal(got, ref)
+        assert st["work_items"] == expected_items(d, q, metric, k, qt, slab, tail)
 
 
 def test_deterministic_repeats(fpm, small):

@@ -638,8 +638,9 @@ static void enqueue_post(fpm_plan *p, uint32_t nq)
 {
     const fpm_index *ix = p->ix;
     const uint32_t qbits = bits_for(std::max<uint32_t>(nq, 1));
-    launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, p->stream);
-    launch_unpack(p->keys, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, p->stream);
+    const uint64_t *sorted =
+        launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, p->stream);
+    launch_unpack(sorted, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, p->stream);
 }
 
 static fpm_status capture(fpm_plan *p, hipGraphExec_t *out, int part, const uint8_t *b, const uint64_t *o,

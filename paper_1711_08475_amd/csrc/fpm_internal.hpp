@@ -23,7 +23,7 @@ namespace fpm {
 constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
 constexpr int kMaxPairs = 2 * 256 * 5;  // (query length, word length) pairs, |dL| <= 2, full + tail part
-constexpr int kRadixBlocks = 64;     // blocks of one stable radix pass (16 waves each)
+constexpr int kRadixBlocks = 128;    // blocks of one stable radix pass (16 waves each)
 
 __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 {
@@ -148,11 +148,11 @@ void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t 
 
 // ----------------------------------------------------------------- sort
 // Stable LSD radix sort of n64 keys (count read from device) on bits
-// [lo_bit, hi_bit); ping-pongs between keys and tmp, the result ends in
-// *keys (data is copied back when the pass count is odd).  scratch:
+// [lo_bit, hi_bit); ping-pongs between keys and tmp and returns the buffer
+// that holds the result (keys for an even pass count, else tmp).  scratch:
 // 256*kRadixBlocks uint32.
-void launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
-                      uint32_t hi_bit, uint32_t *scratch, hipStream_t s);
+const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
+                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s);
 // Packed keys -> fpm_match triples (count read from device, clamped to cap).
 void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,
                    int pairs_only, hipStream_t s);

@@ -416,8 +416,8 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     uint32_t d = K + 1;
     if (act) {
         d = a.survivors_only ? 0u
-                             : verify<METRIC, K>(a.q.str + it.qslot + tq * it.qsw, it.m,
-                                                 a.d.str + it.dslot + te * it.dsw, it.L);
+                             : verify<METRIC, K>(a.q.str + it.qslot + __umul24(tq, it.qsw), it.m,
+                                                 a.d.str + it.dslot + __umul24(te, it.dsw), it.L);
     }
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);
@@ -526,12 +526,12 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                 const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry kChunk padding entries
                 uint32_t msk = 0;
 #pragma unroll
-                for (int t = 0; t < kChunk; ++t)
+                for (int t = kChunk - 1; t >= 0; --t)
                     msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
-                // bit (kChunk - 1 - t) <-> query j0 + t; drop the padding queries
+                // bit t <-> query j0 + t; drop the padding queries
                 // and the lanes past the slab (only on the item's ragged edges)
                 if (nqc < (uint32_t)kChunk || e0 + 64 > it.de) {
-                    msk &= (0xFFFFu << (kChunk - nqc)) & 0xFFFFu;
+                    msk &= (1u << nqc) - 1u;
                     if (!valid)
                         msk = 0;
                 }
@@ -545,11 +545,11 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                     uint32_t pos = 0;
                     if (c)
                         pos = atomicAdd(&qcount[wave], c);
-                    const uint32_t ent0 = ((j0 + kChunk - 1) << kWordBits) | (e - it.ds);
+                    const uint32_t ent0 = (j0 << kWordBits) | (e - it.ds);
                     while (msk) {
-                        const uint32_t bit = 31u - (uint32_t)__builtin_clz(msk);
-                        queue[pos++] = ent0 - (bit << kWordBits);
-                        msk &= ~(1u << bit);
+                        const uint32_t bit = (uint32_t)__builtin_ctz(msk);
+                        queue[pos++] = ent0 + (bit << kWordBits);
+                        msk &= msk - 1u;
                     }
                     __builtin_amdgcn_wave_barrier();
                     const uint32_t nlen = __builtin_amdgcn_readfirstlane(qcount[wave]);

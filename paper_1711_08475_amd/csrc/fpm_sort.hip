@@ -182,13 +182,6 @@ __global__ void __launch_bounds__(256) k_bucket_tables(const uint32_t *offs, uin
         bdw[256] = part[255];
 }
 
-__global__ void k_copy_u64(const uint64_t *src, uint64_t *dst, const uint64_t *dcount, uint64_t cap)
-{
-    const uint64_t n = range_n(dcount, 0, cap);
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
 __global__ void k_unpack(const uint64_t *keys, const uint64_t *dcount, uint64_t cap, uint32_t wbits,
                          uint32_t *triples, int pairs_only)
 {
@@ -216,8 +209,8 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, cons
 {
     hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
-    static_assert(256 * kRadixBlocks % 4096 == 0, "scan table must split into 1024 runs of 4k entries");
-    // kRadixBlocks = 64: 16 entries per scan thread
+    static_assert(256 * kRadixBlocks % 4096 == 0, "scan table must split into 1024 runs of whole uint4s");
+    // kRadixBlocks = 128: 32 entries per scan thread
     hipLaunchKernelGGL(k_scan_exclusive<256 * kRadixBlocks / 1024>, dim3(1), dim3(1024), 0, s, scratch);
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
                        dcount, hcount, cap, shift, scratch);
@@ -232,20 +225,17 @@ void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_
     hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
 }
 
-void launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
-                      uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
+const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
+                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
 {
     uint64_t *a = keys, *b = tmp;
-    int passes = 0;
     for (uint32_t shift = lo_bit; shift < hi_bit; shift += 8) {
         radix_pass<uint64_t>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s);
         uint64_t *t = a;
         a = b;
         b = t;
-        ++passes;
     }
-    if (passes & 1)
-        hipLaunchKernelGGL(k_copy_u64, dim3(1024), dim3(256), 0, s, a, keys, count, cap);
+    return a;
 }
 
 void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,

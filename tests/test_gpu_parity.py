@@ -277,6 +277,20 @@ def test_tail_split(fpm, small, tail):
         assert st["work_items"] == expected_items(d, q, metric, k, qt, slab, tail)
 
 
+@pytest.mark.parametrize("nq", [1, 2, 3, 5, 9, 17, 33, 65, 129, 257, 513])
+def test_match_order_across_key_widths(fpm, small, nq):
+    """The match list is sorted on (query, word) bits whose width depends on
+    the batch size (a different number of radix passes, odd or even); every
+    width must give the oracle's order."""
+    d, q = small
+    qs = datagen.take_csr(q, np.arange(nq))
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    say("key widths", nq)
+    for sched in (0, 1):
+        got = fpm.fpm_match(ix, qs, "lev", 2, fpm.options(schedule=sched))
+        assert np.array_equal(got, oracle.match(d, qs, oracle.LEV, 2))
+
+
 def test_deterministic_repeats(fpm, small):
     d, q = small
     ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")

@@ -12,15 +12,18 @@
 // burst of atomics at start-up), and each wave's issue priority follows its
 // item's position in the list so that items finish about in list order.
 //
-// Per work item, per 64 dictionary words (one per lane) and per 16 queries
-// (their filter keys are wave-uniform, so they sit in scalar registers):
+// Per work item, per 64 dictionary words (one per lane) and per 32 queries
+// (two groups of 16 filter keys, wave-uniform, loaded into scalar registers):
 //   t   = popcount(kq ^ kw) - (2k + 1)   one v_xor, one v_bcnt with accumulator
 //   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
-// i.e. three vector instructions per (query, word) pair.  The lane's 16-bit
+// i.e. three vector instructions per (query, word) pair.  The lane's 32-bit
 // survivor mask is then appended to a per-wave queue in LDS: each lane with
 // survivors reserves its range with one LDS atomic add on the wave's queue
 // counter (the LDS unit serialises the lanes, the VALU computes no prefix
-// sum; entry order does not matter).  Every time the queue holds 64 entries
+// sum; entry order does not matter); when the 32 queries' survivors would
+// not fit, the two halves are appended one after the other with drains in
+// between (every pair survives, e.g., in the brute-force form).  Every time
+// the queue holds 64 entries
 // the wave pops 64 and verifies them, one per lane, so the verifier always
 // runs on full waves.  Matches leave through one atomic per
 // flush of a per-wave LDS staging buffer.
@@ -41,8 +44,8 @@ namespace fpm {
 namespace {
 
 constexpr int kWaves = 4;                 // waves per block, each independent
-constexpr int kChunk = 16;                // queries per filter pass = survivor-mask bits
-constexpr int kQueueCap = 64 * kChunk + 64;  // entries per wave: < 64 left + one full pass
+constexpr int kChunk = 16;                // filter keys per scalar load; a pass covers 2 * kChunk queries
+constexpr int kQueueCap = 64 * kChunk + 64;  // entries per wave: < 64 left + one half pass
 // Matches are staged per wave in LDS and leave through one atomic per flush;
 // a flush happens once more than kOutFlush are staged, so a drain (<= 64
 // new matches) always fits.  Queue + staging + queue counter = 5116 bytes
@@ -521,42 +524,75 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
             const bool valid = e < it.de;
             const Key wk = wk_next;
             wk_next = (e + 64 < it.de) ? dkeys[e + 64] : Key(0);  // next group's key, loaded ahead
-            for (uint32_t j0 = 0; j0 < it.qn; j0 += kChunk) {
-                const uint32_t nqc = min((uint32_t)kChunk, it.qn - j0);
+            for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
+                const uint32_t nqc = min(2u * kChunk, it.qn - j0);
                 const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry kChunk padding entries
                 uint32_t msk = 0;
+                if (nqc > (uint32_t)kChunk) {
+#pragma unroll
+                    for (int t = 2 * kChunk - 1; t >= kChunk; --t)
+                        msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
+                }
 #pragma unroll
                 for (int t = kChunk - 1; t >= 0; --t)
                     msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
                 // bit t <-> query j0 + t; drop the padding queries
                 // and the lanes past the slab (only on the item's ragged edges)
-                if (nqc < (uint32_t)kChunk || e0 + 64 > it.de) {
-                    msk &= (1u << nqc) - 1u;
+                if (nqc < 2u * kChunk || e0 + 64 > it.de) {
+                    if (nqc < 32u)
+                        msk &= (1u << nqc) - 1u;
                     if (!valid)
                         msk = 0;
                 }
                 const uint32_t c = (uint32_t)__builtin_popcount(msk);
                 if (__ballot(c != 0)) {
-                    // queue positions from an LDS atomic per lane (the LDS unit
-                    // hands out the ranges; no VALU prefix sum)
                     if (lane == 0)
                         qcount[wave] = qlen;
                     __builtin_amdgcn_wave_barrier();
                     uint32_t pos = 0;
                     if (c)
                         pos = atomicAdd(&qcount[wave], c);
-                    const uint32_t ent0 = (j0 << kWordBits) | (e - it.ds);
-                    while (msk) {
-                        const uint32_t bit = (uint32_t)__builtin_ctz(msk);
-                        queue[pos++] = ent0 + (bit << kWordBits);
-                        msk &= msk - 1u;
-                    }
                     __builtin_amdgcn_wave_barrier();
-                    const uint32_t nlen = __builtin_amdgcn_readfirstlane(qcount[wave]);
-                    survivors += nlen - qlen;
-                    qlen = nlen;
-                    while (qlen >= 64)
-                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                    const uint32_t tot = __builtin_amdgcn_readfirstlane(qcount[wave]);
+                    const uint32_t ent0 = (j0 << kWordBits) | (e - it.ds);
+                    if (tot <= (uint32_t)kQueueCap) {
+                        while (msk) {
+                            const uint32_t bit = (uint32_t)__builtin_ctz(msk);
+                            queue[pos++] = ent0 + (bit << kWordBits);
+                            msk &= msk - 1u;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        survivors += tot - qlen;
+                        qlen = tot;
+                        while (qlen >= 64)
+                            drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                    } else {
+                        // more survivors than the queue holds: one half at a time
+                        for (uint32_t h = 0; h < 2; ++h) {
+                            uint32_t m = h ? (msk >> kChunk) : (msk & 0xFFFFu);
+                            const uint32_t ch = (uint32_t)__builtin_popcount(m);
+                            if (!__ballot(ch != 0))
+                                continue;
+                            if (lane == 0)
+                                qcount[wave] = qlen;
+                            __builtin_amdgcn_wave_barrier();
+                            uint32_t p = 0;
+                            if (ch)
+                                p = atomicAdd(&qcount[wave], ch);
+                            const uint32_t e1 = ent0 + ((h * kChunk) << kWordBits);
+                            while (m) {
+                                const uint32_t bit = (uint32_t)__builtin_ctz(m);
+                                queue[p++] = e1 + (bit << kWordBits);
+                                m &= m - 1u;
+                            }
+                            __builtin_amdgcn_wave_barrier();
+                            const uint32_t nlen = __builtin_amdgcn_readfirstlane(qcount[wave]);
+                            survivors += nlen - qlen;
+                            qlen = nlen;
+                            while (qlen >= 64)
+                                drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                        }
+                    }
                 }
             }
         }

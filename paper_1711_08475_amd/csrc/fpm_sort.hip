@@ -47,13 +47,44 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_
     hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
 }
 
+// Exclusive prefix of s over a block of 1024 threads: shuffle scans inside
+// each wave, one scan of the 16 wave totals, two barriers.
+__device__ __forceinline__ uint32_t block_exclusive_1024(uint32_t s, uint32_t *wsum)
+{
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint32_t inc = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= (uint32_t)off)
+            inc += y;
+    }
+    if (lane == 63)
+        wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t v = lane < 16 ? wsum[lane] : 0u;
+        uint32_t i2 = v;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t y = __shfl_up(i2, off);
+            if (lane >= (uint32_t)off)
+                i2 += y;
+        }
+        if (lane < 16)
+            wsum[lane] = i2 - v;
+    }
+    __syncthreads();
+    return wsum[w] + inc - s;
+}
+
 // Exclusive scan of the 256 x kRadixBlocks digit table in place, one block
 // of 1024 threads; each thread holds a contiguous run of PER entries in
 // registers (vector loads), so the table is read and written once.
 template <int PER>
 __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
 {
-    __shared__ uint32_t part[1024];
+    __shared__ uint32_t wsum[16];
     const uint32_t t = threadIdx.x;
     uint4 x[PER / 4];
     uint4 *p = (uint4 *)(v + (size_t)t * PER);
@@ -64,15 +95,7 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
 #pragma unroll
     for (int i = 0; i < PER / 4; ++i)
         s += x[i].x + x[i].y + x[i].z + x[i].w;
-    part[t] = s;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        const uint32_t y = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += y;
-        __syncthreads();
-    }
-    uint32_t run = t ? part[t - 1] : 0;
+    uint32_t run = block_exclusive_1024(s, wsum);
 #pragma unroll
     for (int i = 0; i < PER / 4; ++i) {
         uint4 o;

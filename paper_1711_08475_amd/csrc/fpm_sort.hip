@@ -39,10 +39,19 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_
     __syncthreads();
     const uint64_t n = range_n(dcount, hcount, cap);
     const uint64_t lo = n * b / kRadixBlocks, hi = n * (b + 1) / kRadixBlocks;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) {
-        uint32_t d = (uint32_t)(keys[i] >> shift) & 0xFFu;
-        atomicAdd(&h[d], 1u);
+    // eight independent loads in flight per thread before their LDS adds
+    uint64_t i = lo + threadIdx.x;
+    for (; i + 7 * 256 < hi; i += 8 * 256) {
+        uint32_t d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            d[u] = (uint32_t)(keys[i + u * 256] >> shift) & 0xFFu;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            atomicAdd(&h[d[u]], 1u);
     }
+    for (; i < hi; i += 256)
+        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 0xFFu], 1u);
     __syncthreads();
     hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
 }

@@ -56,67 +56,70 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_
     hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
 }
 
-// Exclusive prefix of s over a block of 1024 threads: shuffle scans inside
-// each wave, one scan of the 16 wave totals, two barriers.
-__device__ __forceinline__ uint32_t block_exclusive_1024(uint32_t s, uint32_t *wsum)
+// Inclusive prefix sum over the 64 lanes of a wave (shuffles).
+__device__ __forceinline__ uint32_t wave_inclusive(uint32_t v, uint32_t lane)
 {
-    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    uint32_t inc = s;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(inc, off);
+        const uint32_t y = __shfl_up(v, off);
         if (lane >= (uint32_t)off)
-            inc += y;
+            v += y;
     }
-    if (lane == 63)
-        wsum[w] = inc;
-    __syncthreads();
-    if (w == 0) {
-        const uint32_t v = lane < 16 ? wsum[lane] : 0u;
-        uint32_t i2 = v;
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const uint32_t y = __shfl_up(i2, off);
-            if (lane >= (uint32_t)off)
-                i2 += y;
-        }
-        if (lane < 16)
-            wsum[lane] = i2 - v;
-    }
-    __syncthreads();
-    return wsum[w] + inc - s;
+    return v;
 }
 
-// Exclusive scan of the 256 x kRadixBlocks digit table in place, one block
-// of 1024 threads; each thread holds a contiguous run of PER entries in
-// registers (vector loads), so the table is read and written once.
-template <int PER>
+// Exclusive scan of the digit-major table [256][kRadixBlocks] in place, one
+// block of 16 waves.  Wave w owns digit rows 16w .. 16w+15; a row is read
+// and written coalesced (kRadixBlocks / 64 consecutive entries per lane) and
+// scanned with shuffles; one wave then scans the 256 row totals.
 __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
 {
-    __shared__ uint32_t wsum[16];
-    const uint32_t t = threadIdx.x;
-    uint4 x[PER / 4];
-    uint4 *p = (uint4 *)(v + (size_t)t * PER);
+    constexpr int PL = kRadixBlocks / 64;  // entries per lane and row
+    static_assert(kRadixBlocks % 64 == 0, "rows are split evenly over the lanes");
+    __shared__ uint32_t rowbase[256];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint32_t x[16][PL], ex[16];
 #pragma unroll
-    for (int i = 0; i < PER / 4; ++i)
-        x[i] = p[i];
-    uint32_t s = 0;
+    for (int r = 0; r < 16; ++r)
 #pragma unroll
-    for (int i = 0; i < PER / 4; ++i)
-        s += x[i].x + x[i].y + x[i].z + x[i].w;
-    uint32_t run = block_exclusive_1024(s, wsum);
+        for (int e = 0; e < PL; ++e)
+            x[r][e] = v[(16 * w + r) * kRadixBlocks + lane * PL + e];
 #pragma unroll
-    for (int i = 0; i < PER / 4; ++i) {
-        uint4 o;
-        o.x = run;
-        run += x[i].x;
-        o.y = run;
-        run += x[i].y;
-        o.z = run;
-        run += x[i].z;
-        o.w = run;
-        run += x[i].w;
-        p[i] = o;
+    for (int r = 0; r < 16; ++r) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int e = 0; e < PL; ++e)
+            sum += x[r][e];
+        const uint32_t inc = wave_inclusive(sum, lane);
+        ex[r] = inc - sum;
+        if (lane == 63)
+            rowbase[16 * w + r] = inc;  // row total for now
+    }
+    __syncthreads();
+    if (w == 0) {
+        uint32_t t[4], sum = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            t[e] = rowbase[4 * lane + e];
+            sum += t[e];
+        }
+        uint32_t run = wave_inclusive(sum, lane) - sum;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rowbase[4 * lane + e] = run;
+            run += t[e];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        uint32_t run = rowbase[16 * w + r] + ex[r];
+#pragma unroll
+        for (int e = 0; e < PL; ++e) {
+            const uint32_t c = x[r][e];
+            v[(16 * w + r) * kRadixBlocks + lane * PL + e] = run;
+            run += c;
+        }
     }
 }
 
@@ -241,9 +244,7 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, cons
 {
     hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
-    static_assert(256 * kRadixBlocks % 4096 == 0, "scan table must split into 1024 runs of whole uint4s");
-    // kRadixBlocks = 128: 32 entries per scan thread
-    hipLaunchKernelGGL(k_scan_exclusive<256 * kRadixBlocks / 1024>, dim3(1), dim3(1024), 0, s, scratch);
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, scratch);
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
                        dcount, hcount, cap, shift, scratch);
 }

@@ -49,8 +49,8 @@ constexpr int kQueueCap = 64 * kChunk + 64;  // entries per wave: < 64 left + on
 // Matches are staged per wave in LDS and leave through one atomic per flush;
 // a flush happens once more than kOutFlush are staged, so a drain (<= 64
 // new matches) always fits.  Queue + staging + queue counter = 5116 bytes
-// per wave, at most 20 KB per block: eight blocks fit the 160 KB of LDS of a
-// compute unit.
+// per wave; with the block's exhausted-stripe mask 20,472 bytes per block,
+// so eight blocks fit the 160 KB of LDS of a compute unit.
 constexpr int kOutCap = 95;
 constexpr int kOutFlush = kOutCap - 64;
 
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
             wk_next = (e + 64 < it.de) ? dkeys[e + 64] : Key(0);  // next group's key, loaded ahead
             for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
                 const uint32_t nqc = min(2u * kChunk, it.qn - j0);
-                const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry kChunk padding entries
+                const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
                 uint32_t msk = 0;
                 if (nqc > (uint32_t)kChunk) {
 #pragma unroll

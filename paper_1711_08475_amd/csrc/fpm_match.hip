@@ -12,21 +12,22 @@
 // burst of atomics at start-up), and each wave's issue priority follows its
 // item's position in the list so that items finish about in list order.
 //
-// Per work item, per 64 dictionary words (one per lane) and per 32 queries
-// (two groups of 16 filter keys, wave-uniform, loaded into scalar registers):
+// Per work item, per 128 dictionary words (two per lane, two independent
+// mask chains) and per 32 queries (two groups of 16 filter keys,
+// wave-uniform, loaded into scalar registers):
 //   t   = popcount(kq ^ kw) - (2k + 1)   one v_xor, one v_bcnt with accumulator
 //   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
-// i.e. three vector instructions per (query, word) pair.  The lane's 32-bit
-// survivor mask is then appended to a per-wave queue in LDS: each lane with
-// survivors reserves its range with one LDS atomic add on the wave's queue
-// counter (the LDS unit serialises the lanes, the VALU computes no prefix
-// sum; entry order does not matter); when the 32 queries' survivors would
-// not fit, the two halves are appended one after the other with drains in
-// between (every pair survives, e.g., in the brute-force form).  Every time
-// the queue holds 64 entries
-// the wave pops 64 and verifies them, one per lane, so the verifier always
-// runs on full waves.  Matches leave through one atomic per
-// flush of a per-wave LDS staging buffer.
+// i.e. three vector instructions per (query, word) pair.  Each of the lane's
+// two 32-bit survivor masks is then appended to a per-wave queue in LDS:
+// each lane with survivors reserves its range with one LDS atomic add on
+// the wave's queue counter (the LDS unit serialises the lanes, the VALU
+// computes no prefix sum; entry order does not matter); when 32 queries'
+// survivors would not fit, the two halves are appended one after the other
+// with drains in between (every pair survives, e.g., in the brute-force
+// form).  Every time the queue holds 64 entries the wave pops 64 and
+// verifies them, one per lane, so the verifier always runs on full waves.
+// Matches leave through one atomic per flush of a per-wave LDS staging
+// buffer.
 //
 // Verifiers (k-bounded, exact below k+1):
 //   Ham:   word-parallel mismatch count over 4-byte groups, exit above k;
@@ -518,34 +519,43 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
         set_priority(item, n_items);
         const Item it = decode_item(a, item, n_pairs);
         uint32_t qlen = 0;
-        Key wk_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
-        for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            const bool valid = e < it.de;
-            const Key wk = wk_next;
-            wk_next = (e + 64 < it.de) ? dkeys[e + 64] : Key(0);  // next group's key, loaded ahead
+        // two words per lane: words e0 + lane and e0 + 64 + lane
+        Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
+        Key wb_next = (it.ds + 64 + lane < it.de) ? dkeys[it.ds + 64 + lane] : Key(0);
+        for (uint32_t e0 = it.ds; e0 < it.de; e0 += 128) {
+            const Key wa = wa_next, wb = wb_next;
+            wa_next = (e0 + 128 + lane < it.de) ? dkeys[e0 + 128 + lane] : Key(0);
+            wb_next = (e0 + 192 + lane < it.de) ? dkeys[e0 + 192 + lane] : Key(0);
             for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
                 const uint32_t nqc = min(2u * kChunk, it.qn - j0);
                 const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
-                uint32_t msk = 0;
+                uint32_t ma = 0, mb = 0;
                 if (nqc > (uint32_t)kChunk) {
 #pragma unroll
-                    for (int t = 2 * kChunk - 1; t >= kChunk; --t)
-                        msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
+                    for (int t = 2 * kChunk - 1; t >= kChunk; --t) {
+                        ma = __builtin_amdgcn_alignbit(ma, F::test(qk[t], wa, neg), 31);
+                        mb = __builtin_amdgcn_alignbit(mb, F::test(qk[t], wb, neg), 31);
+                    }
                 }
 #pragma unroll
-                for (int t = kChunk - 1; t >= 0; --t)
-                    msk = __builtin_amdgcn_alignbit(msk, F::test(qk[t], wk, neg), 31);
+                for (int t = kChunk - 1; t >= 0; --t) {
+                    ma = __builtin_amdgcn_alignbit(ma, F::test(qk[t], wa, neg), 31);
+                    mb = __builtin_amdgcn_alignbit(mb, F::test(qk[t], wb, neg), 31);
+                }
                 // bit t <-> query j0 + t; drop the padding queries
                 // and the lanes past the slab (only on the item's ragged edges)
-                if (nqc < 2u * kChunk || e0 + 64 > it.de) {
-                    if (nqc < 32u)
-                        msk &= (1u << nqc) - 1u;
-                    if (!valid)
-                        msk = 0;
+                if (nqc < 2u * kChunk || e0 + 128 > it.de) {
+                    const uint32_t qm = nqc < 32u ? (1u << nqc) - 1u : ~0u;
+                    ma = (e0 + lane < it.de) ? ma & qm : 0u;
+                    mb = (e0 + 64 + lane < it.de) ? mb & qm : 0u;
                 }
-                const uint32_t c = (uint32_t)__builtin_popcount(msk);
-                if (__ballot(c != 0)) {
+#pragma unroll
+                for (uint32_t u = 0; u < 2; ++u) {
+                    uint32_t msk = u ? mb : ma;
+                    const uint32_t e = e0 + 64 * u + lane;
+                    const uint32_t c = (uint32_t)__builtin_popcount(msk);
+                    if (!__ballot(c != 0))
+                        continue;
                     if (lane == 0)
                         qcount[wave] = qlen;
                     __builtin_amdgcn_wave_barrier();

@@ -135,9 +135,12 @@ __device__ __forceinline__ void mask_tail(uint32_t g0, uint32_t len, uint32_t (&
 {
 #pragma unroll
     for (int t = 0; t < D; ++t) {
+        // written with selects only (no min / max), so a uniform length keeps
+        // the mask in scalar registers
         const int rem = (int)len - 4 * (int)(g0 + t);
-        const uint32_t bits = 8u * (uint32_t)min(max(rem, 0), 4);
-        v[t] &= (uint32_t)((1ull << bits) - 1ull);
+        const uint32_t part = (1u << (8u * ((uint32_t)rem & 3u))) - 1u;
+        const uint32_t m = rem >= 4 ? 0xFFFFFFFFu : (rem <= 0 ? 0u : part);
+        v[t] &= m;
     }
 }
 

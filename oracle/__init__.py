@@ -19,6 +19,10 @@ function computes, and the passage of the paper it follows:
 * ``fd``: fingerprint distance F_D (Section 3.3); a pair is rejected when
   ceil(F_D/2) > k (Eq. 1), i.e. survives when F_D <= 2k.
 * ``filter_stats``: examined / surviving pair counts under Eq. 1.
+* ``excess`` / ``filter_stats_asym``: the one-directional halves of F_D and
+  the bound max(excess(q, w), excess(w, q)) <= k built from them -- an
+  extension beyond the paper (it follows from the per-edit argument of
+  Theorem 1 applied to each direction separately), not one of its filters.
 """
 from __future__ import annotations
 
@@ -83,6 +87,13 @@ def _load():
     lib.orc_filter_stats.restype = ctypes.c_int
     lib.orc_filter_stats.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, ctypes.c_int,
                                      ctypes.c_uint32, u8p, ctypes.c_int, ctypes.c_uint32, u64p]
+    lib.orc_excess.restype = ctypes.c_uint32
+    lib.orc_excess.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32]
+    lib.orc_excess_many.restype = None
+    lib.orc_excess_many.argtypes = [u32p, u32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, u32p]
+    lib.orc_filter_stats_asym.restype = ctypes.c_int
+    lib.orc_filter_stats_asym.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, ctypes.c_int,
+                                          ctypes.c_uint32, u8p, ctypes.c_int, ctypes.c_uint32, u64p]
     _lib = lib
     return lib
 
@@ -217,6 +228,34 @@ def fd(a, b, variant: int, bits: int, literal: bool = False):
     _load().orc_fd_many(_ptr(x, ctypes.c_uint32), _ptr(y, ctypes.c_uint32), x.size, variant, bits,
                         1 if literal else 0, _ptr(out, ctypes.c_uint32))
     return out
+
+
+def excess(a, b, variant: int, bits: int):
+    """Excess of fingerprint a over b (occ: fields set in a only; count: sum of
+    positive count differences); scalars or equal-length arrays."""
+    if np.isscalar(a) and np.isscalar(b):
+        return int(_load().orc_excess(int(a), int(b), variant, bits))
+    x = np.ascontiguousarray(a, dtype=np.uint32)
+    y = np.ascontiguousarray(b, dtype=np.uint32)
+    out = np.zeros(x.size, dtype=np.uint32)
+    _load().orc_excess_many(_ptr(x, ctypes.c_uint32), _ptr(y, ctypes.c_uint32), x.size, variant, bits,
+                            _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def filter_stats_asym(dictionary, queries, variant: int, bits: int, mp: np.ndarray, metric: int, k: int):
+    """(examined, survivors) over all pairs under the asymmetric bound
+    max(excess(q, w), excess(w, q)) <= k."""
+    db, do = _csr(dictionary)
+    qb, qo = _csr(queries)
+    m = np.ascontiguousarray(mp, dtype=np.uint8)
+    c = np.zeros(2, dtype=np.uint64)
+    rc = _load().orc_filter_stats_asym(_ptr(db, ctypes.c_uint8), _ptr(do, ctypes.c_uint64), do.size - 1,
+                                       _ptr(qb, ctypes.c_uint8), _ptr(qo, ctypes.c_uint64), qo.size - 1, variant,
+                                       bits, _ptr(m, ctypes.c_uint8), metric, k, _ptr(c, ctypes.c_uint64))
+    if rc != 0:
+        raise ValueError("bad symbol map or variant")
+    return int(c[0]), int(c[1])
 
 
 def filter_stats(dictionary, queries, variant: int, bits: int, mp: np.ndarray, metric: int, k: int):

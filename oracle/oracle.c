@@ -611,6 +611,43 @@ uint32_t orc_fd(uint32_t a, uint32_t b, int variant, uint32_t bits, int literal)
     }
 }
 
+/* Excess of fingerprint a over fingerprint b -- the one-directional half
+ * of F_D used by the asymmetric bound (an extension beyond the paper's
+ * Eq. 1, not one of its filters):
+ *   occ, occ-halved: number of fields set in a and clear in b;
+ *   count: sum over fields of max(c_a - c_b, 0) of the saturated counts;
+ *   pos: not defined (ORC_INF).
+ * excess(a, b) + excess(b, a) = F_D.  One edit changes each direction's
+ * excess by at most one (a field can only gain or lose one unit), so the
+ * distance is at least max(excess(a, b), excess(b, a)), which is itself at
+ * least ceil(F_D / 2): a pair can be rejected when either excess exceeds k.
+ * (For occ-halved this holds for Hamming only, as F_D itself does.) */
+uint32_t orc_excess(uint32_t a, uint32_t b, int variant, uint32_t bits)
+{
+    switch (variant) {
+    case ORC_OCC:
+    case ORC_OCCH:
+        return popcount32(a & ~b);
+    case ORC_COUNT: {
+        uint32_t d = 0;
+        for (uint32_t j = 0; j < bits / 2; ++j) {
+            int ca = (int)((a >> (2 * j)) & 3u), cb = (int)((b >> (2 * j)) & 3u);
+            if (ca > cb)
+                d += (uint32_t)(ca - cb);
+        }
+        return d;
+    }
+    default:
+        return ORC_INF;
+    }
+}
+
+void orc_excess_many(const uint32_t *a, const uint32_t *b, uint64_t n, int variant, uint32_t bits, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = orc_excess(a[i], b[i], variant, bits);
+}
+
 /* Filter statistics over all (query, word) pairs.  A pair is examined when
  * it can match at all by length (Ham: equal lengths; Lev: |m-n| <= k); it
  * survives when ceil(F_D/2) <= k, i.e. F_D <= 2k (Eq. 1).  counts[0] =
@@ -642,6 +679,39 @@ int orc_filter_stats(const uint8_t *dbytes, const uint64_t *doffs, uint32_t nd,
                 counts[1]++;
             if (orc_fd(qfp, dfp[w], variant, bits, 1) <= 2 * k)
                 counts[2]++;
+        }
+    }
+    free(dfp);
+    return 0;
+}
+
+/* Filter statistics under the asymmetric bound: counts[0] = examined
+ * (as in orc_filter_stats), counts[1] = pairs with
+ * max(excess(q, w), excess(w, q)) <= k. */
+int orc_filter_stats_asym(const uint8_t *dbytes, const uint64_t *doffs, uint32_t nd,
+                          const uint8_t *qbytes, const uint64_t *qoffs, uint32_t nq,
+                          int variant, uint32_t bits, const uint8_t *map, int metric, uint32_t k,
+                          uint64_t counts[2])
+{
+    if (orc_check_map(map, variant, bits) || variant == ORC_POS)
+        return -1;
+    uint32_t *dfp = (uint32_t *)malloc(sizeof(uint32_t) * (nd ? nd : 1));
+    if (!dfp)
+        return -1;
+    orc_fp_many(dbytes, doffs, nd, variant, bits, map, dfp);
+    counts[0] = counts[1] = 0;
+    for (uint32_t q = 0; q < nq; ++q) {
+        uint32_t m = (uint32_t)(qoffs[q + 1] - qoffs[q]);
+        uint32_t qfp = orc_fp(qbytes + qoffs[q], m, variant, bits, map);
+        for (uint32_t w = 0; w < nd; ++w) {
+            uint32_t n = (uint32_t)(doffs[w + 1] - doffs[w]);
+            uint32_t gap = m > n ? m - n : n - m;
+            int examined = metric == ORC_HAM ? gap == 0 : gap <= k;
+            if (!examined)
+                continue;
+            counts[0]++;
+            if (orc_excess(qfp, dfp[w], variant, bits) <= k && orc_excess(dfp[w], qfp, variant, bits) <= k)
+                counts[1]++;
         }
     }
     free(dfp);

@@ -79,6 +79,22 @@ typedef enum { FPM_COMMON = 0, FPM_RARE = 1, FPM_MIXED = 2, FPM_CUSTOM = 3 } fpm
  *     verified (the paper's naive comparison T_n, Section 4). */
 typedef enum { FPM_SCHED_PLAIN = 0, FPM_SCHED_BATCHED = 1, FPM_SCHED_BRUTE = 2 } fpm_schedule;
 
+/* Rejection rule of the filter.
+ *   FPM_BOUND_FD: the paper's Eq. 1 -- a pair survives when F_D <= 2k.
+ *   FPM_BOUND_ASYM: an extension beyond the paper, offered as a separate
+ *     rule so the paper's filter stays as printed.  F_D splits into
+ *     e(q, w) = popc(q & ~w) and e(w, q) = popc(w & ~q) (count: the sums of
+ *     positive count differences); the per-edit argument of Theorem 1,
+ *     applied to each direction alone, gives D >= max(e(q, w), e(w, q)) >=
+ *     ceil(F_D / 2), so a pair survives when both are <= k.  Since
+ *     e(q, w) - e(w, q) = popc(q) - popc(w), pairs whose key popcounts differ
+ *     by more than k are rejected wholesale: dictionary length blocks are
+ *     ordered by popcount and work tiles whose popcount ranges are too far
+ *     apart are skipped.  Defined for occurrence, occurrence-halved (Hamming)
+ *     and count fingerprints; FPM_EUNSUPPORTED for position fingerprints.
+ *     Matches are the same under both rules; survivors differ. */
+typedef enum { FPM_BOUND_FD = 0, FPM_BOUND_ASYM = 1 } fpm_bound;
+
 /* One reported match.  `query` and `word` index the caller's lists. */
 typedef struct {
     uint32_t query;
@@ -90,7 +106,7 @@ typedef struct {
 typedef struct {
     uint64_t pairs_logical;  /* |Q| * |D| */
     uint64_t pairs_examined; /* length-compatible pairs put through the filter */
-    uint64_t survivors;      /* pairs kept by the filter (F_D <= 2k) and verified */
+    uint64_t survivors;      /* pairs kept by the filter (F_D <= 2k, or the asymmetric bound) and verified */
     uint64_t matches;        /* pairs within distance k */
     uint64_t verify_cells;   /* sum over survivors of (2k+1) * min(m, n) */
     float ms;                /* device time of the match pipeline (hip events) */
@@ -114,7 +130,8 @@ typedef struct {
                                   into tail items of a smaller tile (queries_per_item / 2 by slab / 4,
                                   at least 16 by 64), listed after every full-size item so that a launch
                                   ends on short items; 0 = default (100: no tail items) */
-    uint32_t reserved[7];
+    uint32_t bound;            /* fpm_bound: filter rule (default FPM_BOUND_FD); ignored by FPM_SCHED_BRUTE */
+    uint32_t reserved[6];
 } fpm_options;
 
 typedef struct fpm_index fpm_index;

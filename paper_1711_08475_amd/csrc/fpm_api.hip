@@ -64,7 +64,17 @@ int key_kind_for(int variant, uint32_t bits)
     return kPop32;
 }
 
-size_t key_bytes(int kind) { return kind == kPop64 ? 8 : 4; }
+// Keys for the asymmetric bound; -1 where it is not defined (position).
+int key_kind_asym(int variant, uint32_t bits)
+{
+    if (variant == FPM_POS)
+        return -1;
+    if (variant == FPM_COUNT)
+        return bits == 32 ? kAsym64 : kAsym32;
+    return bits == 16 ? kTherm32 : kAsym32;
+}
+
+size_t key_bytes(int kind) { return key_is_64(kind) ? 8 : 4; }
 
 fpm_status check_csr(const uint8_t *bytes, const uint64_t *offsets, uint32_t n, const char *what)
 {
@@ -88,8 +98,10 @@ struct StrSet {
     void *key = nullptr;
     uint32_t *fp_orig = nullptr;
     uint32_t *inv = nullptr;
+    uint32_t *ck = nullptr, *tmp_k = nullptr, *tmp_v = nullptr;  // (length, popcount) ordering
 
-    hipError_t alloc(uint32_t max_n, uint64_t max_bytes, int kind, bool want_fp_orig, bool want_inv)
+    hipError_t alloc(uint32_t max_n, uint64_t max_bytes, int kind, bool want_fp_orig, bool want_inv,
+                     bool want_pop_order)
     {
         cap_n = max_n;
         cap_bytes = max_bytes;
@@ -111,6 +123,8 @@ struct StrSet {
             return e;
         if (want_inv && (e = dalloc(&inv, max_n)))
             return e;
+        if (want_pop_order && ((e = dalloc(&ck, max_n)) || (e = dalloc(&tmp_k, max_n)) || (e = dalloc(&tmp_v, max_n))))
+            return e;
         return hipSuccess;
     }
     void release()
@@ -125,23 +139,38 @@ struct StrSet {
         dfree(key);
         dfree(fp_orig);
         dfree(inv);
+        dfree(ck);
+        dfree(tmp_k);
+        dfree(tmp_v);
     }
     StrSetView view() const { return StrSetView{perm, slen, soff, str, off, key}; }
 };
 
-// Length sort, padded layout and fingerprints of n device strings.
+// Length sort, padded layout and fingerprints of n device strings.  With
+// pop_order (needs the StrSet's ordering buffers) each length block is
+// further ordered by the popcount of the filter key: the first layout only
+// yields those popcounts, the set is then laid out again in the final order.
 void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, uint32_t n, uint64_t nbytes_limit,
-                  const uint8_t *d_map, int variant, uint32_t bits, int kind, bool fingerprints, uint32_t *err,
-                  uint32_t *scratch, hipStream_t s)
+                  const uint8_t *d_map, int variant, uint32_t bits, int kind, bool fingerprints, bool pop_order,
+                  uint32_t *err, uint32_t *scratch, hipStream_t s)
 {
     S.n = n;
     launch_lengths(d_offsets, n, S.len, err, s);
     launch_length_sort(S.len, n, S.perm, S.off, S.bdw, scratch, s);
     launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str, S.str_cap,
                   err, s);
-    if (fingerprints)
-        launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, S.fp_orig, S.key,
-                            kind, s);
+    if (!fingerprints)
+        return;
+    if (pop_order) {
+        launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, nullptr, S.key, kind,
+                            s);
+        launch_len_pop_keys(S.perm, S.slen, S.key, kind, n, S.ck, s);
+        launch_len_pop_sort(S.ck, n, S.perm, S.off, S.bdw, S.tmp_k, S.tmp_v, scratch, s);
+        launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str,
+                      S.str_cap, err, s);
+    }
+    launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, S.fp_orig, S.key, kind,
+                        s);
 }
 
 struct DevCounters {
@@ -157,6 +186,7 @@ struct fpm_index {
     int variant = 0;
     uint32_t bits = 16;
     int kind = kPop32;
+    int kind_asym = -1;  // keys of the asymmetric bound (-1: not defined)
     uint8_t map[256];
     uint8_t *d_map = nullptr;
     StrSet words;
@@ -175,9 +205,15 @@ struct fpm_plan {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int kind = kPop32;
+    bool asym = false;  // asymmetric bound: query blocks ordered by popcount too
     bool survivors_only = false;
 
     StrSet q;
+    // asymmetric bound: the dictionary with every length block ordered by
+    // key popcount (own strings, permutation and keys; lengths, slot offsets
+    // and block tables are the index's)
+    uint32_t *a_perm = nullptr, *a_str = nullptr;
+    void *a_key = nullptr;
     uint32_t *scratch = nullptr;
     PairRec *pairs = nullptr;
     DevCounters *ctr = nullptr;
@@ -346,6 +382,7 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     ix->variant = variant;
     ix->bits = bits;
     ix->kind = key_kind_for(variant, bits);
+    ix->kind_asym = key_kind_asym(variant, bits);
     ix->wbits = bits_for(n_words);
     (void)hipGetDevice(&ix->device);
 
@@ -367,7 +404,7 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&d_bytes, nbytes + 4)) ||
         (e = dalloc(&d_off, (size_t)n_words + 1)) || (e = dalloc(&d_hist, 256)) ||
         (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&d_err, 1)) || (e = dalloc(&ix->d_map, 256)) ||
-        (e = ix->words.alloc(n_words, nbytes, ix->kind, true, true))) {
+        (e = ix->words.alloc(n_words, nbytes, ix->kind, true, true, false))) {
         cleanup();
         fpm_index_destroy(ix);
         return hip_fail(e, "fpm_build_fingerprints alloc");
@@ -383,8 +420,8 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
         launch_byte_histogram(d_bytes, d_off, n_words, d_hist, s);
         launch_select_symbols(d_hist, nf, (int)symbols, ix->d_map, s);
     }
-    prep_strings(ix->words, d_bytes, d_off, n_words, nbytes, ix->d_map, variant, bits, ix->kind, true, d_err, scratch,
-                 s);
+    prep_strings(ix->words, d_bytes, d_off, n_words, nbytes, ix->d_map, variant, bits, ix->kind, true, false, d_err,
+                 scratch, s);
     launch_invert(ix->words.perm, n_words, ix->words.inv, s);
     (void)hipMemcpyAsync(ix->map, ix->d_map, 256, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(ix->h_off, ix->words.off, sizeof(uint32_t) * 257, hipMemcpyDeviceToHost, s);
@@ -445,6 +482,9 @@ static void plan_free(fpm_plan *p)
             if (p->kev[i][j])
                 (void)hipEventDestroy(p->kev[i][j]);
     p->q.release();
+    dfree(p->a_perm);
+    dfree(p->a_str);
+    dfree(p->a_key);
     dfree(p->scratch);
     dfree(p->pairs);
     dfree(p->ctr);
@@ -504,6 +544,50 @@ static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
         o->tail_split = 100;
     if (o->tail_split > 100)
         return fail(FPM_EINVAL, "tail_split must be in 1..100 (0 = default)");
+    if (o->bound > FPM_BOUND_ASYM)
+        return fail(FPM_EINVAL, "unknown bound %u", o->bound);
+    return FPM_OK;
+}
+
+// The dictionary of an asymmetric-bound plan: the index's length blocks,
+// each ordered by key popcount (stable), with keys of the bound's family.
+// Runs once at plan creation and waits for it.
+static fpm_status build_asym_dictionary(fpm_plan *p)
+{
+    const fpm_index *ix = p->ix;
+    const StrSet &W = ix->words;
+    const uint32_t n = ix->n;
+    hipStream_t s = p->stream;
+    uint32_t *ck = nullptr, *src = nullptr, *tk = nullptr, *tv = nullptr, *off = nullptr, *bdw = nullptr;
+    auto cleanup = [&]() {
+        dfree(ck);
+        dfree(src);
+        dfree(tk);
+        dfree(tv);
+        dfree(off);
+        dfree(bdw);
+    };
+    const size_t kb = ((size_t)n + 64) * key_bytes(p->kind);
+    hipError_t e;
+    if ((e = dalloc(&p->a_perm, std::max<uint32_t>(n, 1))) || (e = dalloc(&p->a_str, W.str_cap)) ||
+        (e = dalloc((uint8_t **)&p->a_key, kb)) || (e = dalloc(&ck, std::max<uint32_t>(n, 1))) ||
+        (e = dalloc(&src, std::max<uint32_t>(n, 1))) || (e = dalloc(&tk, std::max<uint32_t>(n, 1))) ||
+        (e = dalloc(&tv, std::max<uint32_t>(n, 1))) || (e = dalloc(&off, 257)) || (e = dalloc(&bdw, 257)) ||
+        (e = hipMemsetAsync(p->a_str, 0, W.str_cap * sizeof(uint32_t), s)) || (e = hipMemsetAsync(p->a_key, 0, kb, s))) {
+        cleanup();
+        return hip_fail(e, "asymmetric-bound dictionary alloc");
+    }
+    launch_len_pop_keys(nullptr, W.slen, W.key, ix->kind, n, ck, s);
+    launch_len_pop_sort(ck, n, src, off, bdw, tk, tv, p->scratch, s);
+    launch_gather_slots(src, W.perm, W.slen, W.soff, W.str, n, p->a_str, p->a_perm, s);
+    launch_fingerprints(p->a_str, W.soff, W.slen, p->a_perm, n, ix->d_map, ix->variant, (int)ix->bits, nullptr,
+                        nullptr, p->a_key, p->kind, s);
+    e = hipStreamSynchronize(s);
+    if (!e)
+        e = hipGetLastError();
+    cleanup();
+    if (e)
+        return hip_fail(e, "asymmetric-bound dictionary");
     return FPM_OK;
 }
 
@@ -537,7 +621,12 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     p->metric = metric;
     p->k = k;
     p->survivors_only = survivors_only;
-    p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : ix->kind;
+    p->asym = p->opt.bound == FPM_BOUND_ASYM && p->opt.schedule != FPM_SCHED_BRUTE;
+    if (p->asym && ix->kind_asym < 0) {
+        delete p;
+        return fail(FPM_EUNSUPPORTED, "the asymmetric bound is not defined for position fingerprints");
+    }
+    p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : p->asym ? ix->kind_asym : ix->kind;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;
@@ -546,13 +635,15 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         p->own_stream = true;
     }
     const int qkind = p->kind == kAll ? kPop32 : p->kind;
-    if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false)) ||
+    if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false, p->asym)) ||
         (e = dalloc(&p->scratch, 256u * kRadixBlocks)) || (e = dalloc(&p->pairs, kMaxPairs)) ||
         (e = dalloc(&p->ctr, 1)) || (e = hipEventCreate(&p->ev0)) || (e = hipEventCreate(&p->ev1))) {
         plan_free(p);
         return hip_fail(e, "fpm_plan_create alloc");
     }
     st = p->alloc_output(p->opt.match_capacity);
+    if (!st && p->asym)
+        st = build_asym_dictionary(p);
     if (st) {
         plan_free(p);
         return st;
@@ -594,7 +685,7 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     launch_zero(p->ctr, sizeof(DevCounters) / 4, s);
     const bool fps = p->kind != kAll;
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
-                 fps ? p->kind : kPop32, fps, &p->ctr->err, p->scratch, s);
+                 fps ? p->kind : kPop32, fps, p->asym, &p->ctr->err, p->scratch, s);
     if (plain) {
         uint32_t h_qoff[257];
         HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));
@@ -621,6 +712,11 @@ static fpm_status enqueue_kernel(fpm_plan *p, bool plain)
     MatchArgs a;
     a.q = p->q.view();
     a.d = ix->words.view();
+    if (p->asym) {
+        a.d.perm = p->a_perm;
+        a.d.str = p->a_str;
+        a.d.key = p->a_key;
+    }
     a.wl = p->worklist();
     a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells};
     a.out_keys = p->keys;
@@ -932,13 +1028,13 @@ struct TmpSet {
         hipError_t e;
         if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&b, nbytes + 4)) ||
             (e = dalloc(&o, (size_t)n + 1)) || (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&err, 1)) ||
-            (e = S.alloc(n, nbytes + 4, ix->kind, fp_orig, true)))
+            (e = S.alloc(n, nbytes + 4, ix->kind, fp_orig, true, false)))
             return hip_fail(e, "temporary string set");
         if (nbytes)
             (void)hipMemcpyAsync(b, bytes, nbytes, hipMemcpyHostToDevice, s);
         (void)hipMemcpyAsync(o, offsets, sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s);
         launch_zero(err, 1, s);
-        prep_strings(S, b, o, n, nbytes, ix->d_map, ix->variant, ix->bits, ix->kind, true, err, scratch, s);
+        prep_strings(S, b, o, n, nbytes, ix->d_map, ix->variant, ix->bits, ix->kind, true, false, err, scratch, s);
         launch_invert(S.perm, n, S.inv, s);
         return FPM_OK;
     }

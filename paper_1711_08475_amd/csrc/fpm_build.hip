@@ -211,14 +211,49 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
         // the counts.
         const uint32_t lo = fp & 0x55555555u, hi = (fp >> 1) & 0x55555555u;
         const uint32_t t0 = lo | hi, t1 = hi, t2 = lo & hi;
-        if (key_kind == kPop64) {
+        if (key_is_64(key_kind)) {
             ((uint64_t *)keys)[p] = (uint64_t)(t0 | (t1 << 1)) | ((uint64_t)t2 << 32);
         } else {
             ((uint32_t *)keys)[p] = (t0 | (t1 << 1)) | (t2 << 16);  // 8 fields: bits 0..15 and 16..30
         }
+    } else if (key_kind == kTherm32) {
+        // 16-bit fingerprint, thermometer code of its popcount above it
+        ((uint32_t *)keys)[p] = fp | (((1u << __builtin_popcount(fp)) - 1u) << 16);
     } else {
         ((uint32_t *)keys)[p] = fp;
     }
+}
+
+__global__ void k_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
+                               uint32_t *ck)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    uint32_t pop;
+    if (key_is_64(key_kind))
+        pop = (uint32_t)__popcll(((const uint64_t *)keys)[p]);
+    else
+        pop = (uint32_t)__builtin_popcount(((const uint32_t *)keys)[p]);
+    ck[perm ? perm[p] : p] = ((uint32_t)slen[p] << 8) | pop;
+}
+
+// Reorder a laid-out set inside its length blocks: new position p takes the
+// string at old position src[p] (same block, so same slot size; slot
+// offsets and lengths are per position and stay as they are).
+__global__ void k_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
+                               const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint32_t o = src[p];
+    const uint32_t sw = slot_dwords(slen[p]);
+    const uint32_t *in = str + soff[o];
+    uint32_t *out = str_out + soff[p];
+    for (uint32_t t = 0; t < sw; ++t)
+        out[t] = in[t];
+    perm_out[p] = perm[o];
 }
 
 __global__ void k_invert(const uint32_t *perm, uint32_t n, uint32_t *inv)
@@ -293,6 +328,23 @@ void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_
                            keys, key_kind);
         break;
     }
+}
+
+void launch_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
+                         uint32_t *ck, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    hipLaunchKernelGGL(k_len_pop_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, slen, keys, key_kind, n, ck);
+}
+
+void launch_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
+                         const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, perm, slen, soff, str, n,
+                       str_out, perm_out);
 }
 
 void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t s)

@@ -34,7 +34,16 @@ __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 // occ-halved, 16-bit count thermometer); Pop64: the same on 64-bit keys
 // (32-bit count thermometer); Pos16 / Pos32: position fingerprints; All: no
 // filter (brute force, every length-compatible pair is verified).
-enum KeyKind : int { kPop32 = 0, kPop64 = 1, kPos16 = 2, kPos32 = 3, kAll = 4 };
+// The asymmetric bound max(popc(q & ~w), popc(w & ~q)) <= k (an extension
+// of Eq. 1, sound wherever F_D is) uses:
+//   Therm32: a 16-bit key with the thermometer code of its own popcount in
+//            bits 16..31, so popc(kq ^ kw) = F_D + |pq - pw| = twice the
+//            larger excess and the Pop32 test applies unchanged;
+//   Asym32 / Asym64: the Pop32 / Pop64 keys, tested as
+//            popc(~(q & w)) + max(pq, pw) against the key width + k + 1.
+enum KeyKind : int { kPop32 = 0, kPop64 = 1, kPos16 = 2, kPos32 = 3, kAll = 4, kTherm32 = 5, kAsym32 = 6, kAsym64 = 7 };
+
+__host__ __device__ inline bool key_is_64(int kind) { return kind == kPop64 || kind == kAsym64; }
 
 struct StrSetView {
     const uint32_t *perm;  // sorted -> caller index
@@ -95,6 +104,24 @@ void launch_byte_histogram(const uint8_t *bytes, const uint64_t *offsets, uint32
                            hipStream_t s);
 // Symbol map from a histogram (common / rare / mixed), map_out[256].
 void launch_select_symbols(const unsigned long long *hist, int nfields, int symset, uint8_t *map_out, hipStream_t s);
+
+// Composite sort keys (length << 8 | key popcount) from the keys of a
+// length-sorted set: ck[perm[p]] for sorted position p (caller order), or
+// ck[p] when perm is null (position order).
+void launch_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
+                         uint32_t *ck, hipStream_t s);
+
+// Reorder a laid-out set inside its length blocks: position p of the output
+// takes the padded string and caller index of old position src[p] (src
+// must map each block onto itself).  Lengths and slot offsets are shared.
+void launch_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
+                         const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out, hipStream_t s);
+
+// Stable sort of indices 0..n-1 by (length, popcount) from composite keys
+// (two 8-bit radix passes); same outputs as launch_length_sort.  tmp_k and
+// tmp_v: n uint32 each.
+void launch_len_pop_sort(const uint32_t *ck, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
+                         uint32_t *tmp_k, uint32_t *tmp_v, uint32_t *scratch, hipStream_t s);
 
 // Stable sort of indices 0..n-1 by length (a single 8-bit radix pass).
 // Writes perm (sorted -> caller index), off[257] bucket offsets and

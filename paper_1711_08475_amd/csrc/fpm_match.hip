@@ -111,6 +111,136 @@ struct Filter<kAll> {
     static __device__ __forceinline__ uint32_t test(Key, Key, uint32_t) { return 0x80000000u; }
 };
 
+// Asymmetric bound, thermometer form: the key's upper half holds the
+// thermometer code of the popcount of its lower half, so the XOR weight is
+// F_D + |pq - pw| = 2 max(e(q, w), e(w, q)) and the F_D <= 2k test applies.
+template <>
+struct Filter<kTherm32> : Filter<kPop32> {
+};
+
+// Asymmetric bound on full-width keys: with c = popc(q & w) the larger
+// excess is max(pq, pw) - c, and it is <= k iff
+// popc(~(q & w)) + max(pq, pw) - (width + k + 1) < 0.  Each side's popcount
+// plus `neg` = -(width + k + 1) is computed once per query (scalar) and once
+// per word (vector), so a pair costs a NAND, a max and the popcount that
+// accumulates onto the max.  The empty asm statements keep the compiler
+// from pulling the shared bias out of the max (which would add one more
+// instruction per pair).
+__device__ __forceinline__ uint32_t opaque_v(uint32_t x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x)
+{
+    asm("" : "+s"(x));
+    return x;
+}
+
+template <>
+struct Filter<kAsym32> {
+    using Key = uint32_t;
+    static __device__ __forceinline__ uint32_t side_w(Key w, uint32_t neg)
+    {
+        return opaque_v((uint32_t)__builtin_popcount(w) + neg);
+    }
+    static __device__ __forceinline__ uint32_t side_q(Key q, uint32_t neg)
+    {
+        return opaque_s((uint32_t)__builtin_popcount(q) + neg);
+    }
+    static __device__ __forceinline__ uint32_t test(Key q, uint32_t sq, Key w, uint32_t sw)
+    {
+        return (uint32_t)__builtin_popcount(~(q & w)) + (uint32_t)max((int)sq, (int)sw);
+    }
+};
+
+template <>
+struct Filter<kAsym64> {
+    using Key = uint64_t;
+    static __device__ __forceinline__ uint32_t side_w(Key w, uint32_t neg)
+    {
+        return opaque_v((uint32_t)__popcll(w) + neg);
+    }
+    static __device__ __forceinline__ uint32_t side_q(Key q, uint32_t neg)
+    {
+        return opaque_s((uint32_t)__popcll(q) + neg);
+    }
+    static __device__ __forceinline__ uint32_t test(Key q, uint32_t sq, Key w, uint32_t sw)
+    {
+        const uint64_t x = ~(q & w);
+        return (uint32_t)__builtin_popcount((uint32_t)(x >> 32)) +
+               ((uint32_t)__builtin_popcount((uint32_t)x) + (uint32_t)max((int)sq, (int)sw));
+    }
+};
+
+// -(threshold + 1) of each key family's test.
+template <int KIND, int K>
+__host__ __device__ constexpr uint32_t filter_neg()
+{
+    return KIND == kAsym32 ? 0u - (32u + K + 1u) : KIND == kAsym64 ? 0u - (64u + K + 1u) : 0u - (2u * K + 1u);
+}
+
+// Families of the asymmetric bound: e(q, w) - e(w, q) = pq - pw, so a pair
+// whose key popcounts differ by more than pop_gap (in key popcount units:
+// 2k for the thermometer keys, k otherwise) cannot survive.  Their blocks
+// are ordered by popcount, so a tile spans [pop(first), pop(last)].
+template <int KIND>
+__host__ __device__ constexpr bool pop_skip()
+{
+    return KIND == kTherm32 || KIND == kAsym32 || KIND == kAsym64;
+}
+
+template <int KIND>
+__host__ __device__ constexpr bool side_values()
+{
+    return KIND == kAsym32 || KIND == kAsym64;
+}
+
+// One query against the lane's two words: the test's sign bit goes into bit
+// 0 of each mask (older bits move up).  sa / sb: the words' side values.
+template <int KIND>
+__device__ __forceinline__ void filter_step(typename Filter<KIND>::Key q, typename Filter<KIND>::Key wa,
+                                            typename Filter<KIND>::Key wb, uint32_t sa, uint32_t sb, uint32_t neg,
+                                            uint32_t &ma, uint32_t &mb)
+{
+    using F = Filter<KIND>;
+    if constexpr (side_values<KIND>()) {
+        const uint32_t sq = F::side_q(q, neg);
+        ma = __builtin_amdgcn_alignbit(ma, F::test(q, sq, wa, sa), 31);
+        mb = __builtin_amdgcn_alignbit(mb, F::test(q, sq, wb, sb), 31);
+    } else {
+        ma = __builtin_amdgcn_alignbit(ma, F::test(q, wa, neg), 31);
+        mb = __builtin_amdgcn_alignbit(mb, F::test(q, wb, neg), 31);
+    }
+}
+
+template <int KIND, int K>
+__host__ __device__ constexpr uint32_t pop_gap()
+{
+    return KIND == kTherm32 ? 2u * K : (uint32_t)K;
+}
+
+__device__ __forceinline__ uint32_t key_pop(uint32_t v) { return (uint32_t)__builtin_popcount(v); }
+__device__ __forceinline__ uint32_t key_pop(uint64_t v) { return (uint32_t)__popcll(v); }
+
+// Wave-uniform copy of lane l's key (l uniform).
+__device__ __forceinline__ uint32_t lane_key(uint32_t v, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+__device__ __forceinline__ uint64_t lane_key(uint64_t v, uint32_t l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Two popcount ranges that no pair can bridge.
+__device__ __forceinline__ bool pop_apart(uint32_t alo, uint32_t ahi, uint32_t blo, uint32_t bhi, uint32_t gap)
+{
+    return alo > bhi + gap || blo > ahi + gap;
+}
+
 // ------------------------------------------------------------ verifiers
 // All verifiers see wave-uniform lengths (every entry of a drain comes from
 // one work item, i.e. one pair of length buckets), so loop trip counts and
@@ -508,7 +638,9 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     uint32_t ocount = 0;
     const cptr<Key> qkeys = as_const((const Key *)a.q.key);
     const Key *__restrict__ dkeys = (const Key *)a.d.key;
-    const uint32_t neg = 0u - (2u * K + 1u);
+    const uint32_t neg = filter_neg<KIND, K>();
+    constexpr bool kSkip = pop_skip<KIND>();
+    constexpr uint32_t kGap = pop_gap<KIND, K>();
     const uint32_t n_items = *as_const(a.wl.n_items);
     const uint32_t n_pairs = *as_const(a.wl.n_pairs);
     uint64_t survivors = 0, cells = 0;
@@ -520,7 +652,14 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     uint32_t item = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
     while (item < n_items) {
         set_priority(item, n_items);
-        const Item it = decode_item(a, item, n_pairs);
+        Item it = decode_item(a, item, n_pairs);
+        if constexpr (kSkip) {
+            // the whole tile is out of popcount reach: nothing to do
+            if (it.qn && it.de > it.ds &&
+                pop_apart(key_pop(qkeys[it.qs]), key_pop(qkeys[it.qs + it.qn - 1]),
+                          key_pop(lane_key(dkeys[it.ds], 0)), key_pop(lane_key(dkeys[it.de - 1], 0)), kGap))
+                it.de = it.ds;
+        }
         uint32_t qlen = 0;
         // two words per lane: words e0 + lane and e0 + 64 + lane
         Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
@@ -529,22 +668,34 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
             const Key wa = wa_next, wb = wb_next;
             wa_next = (e0 + 128 + lane < it.de) ? dkeys[e0 + 128 + lane] : Key(0);
             wb_next = (e0 + 192 + lane < it.de) ? dkeys[e0 + 192 + lane] : Key(0);
+            uint32_t glo = 0, ghi = 0;
+            if constexpr (kSkip) {
+                // popcount range of this group of 128 words (ascending)
+                const uint32_t last = min(e0 + 127u, it.de - 1u) - e0;
+                glo = key_pop(lane_key(wa, 0));
+                ghi = key_pop(last >= 64u ? lane_key(wb, last - 64u) : lane_key(wa, last));
+            }
+            uint32_t sa = 0, sb = 0;
+            if constexpr (side_values<KIND>()) {
+                sa = F::side_w(wa, neg);
+                sb = F::side_w(wb, neg);
+            }
             for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
                 const uint32_t nqc = min(2u * kChunk, it.qn - j0);
                 const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
+                if constexpr (kSkip) {
+                    if (pop_apart(key_pop(qk[0]), key_pop(qk[nqc - 1]), glo, ghi, kGap))
+                        continue;
+                }
                 uint32_t ma = 0, mb = 0;
                 if (nqc > (uint32_t)kChunk) {
 #pragma unroll
-                    for (int t = 2 * kChunk - 1; t >= kChunk; --t) {
-                        ma = __builtin_amdgcn_alignbit(ma, F::test(qk[t], wa, neg), 31);
-                        mb = __builtin_amdgcn_alignbit(mb, F::test(qk[t], wb, neg), 31);
-                    }
+                    for (int t = 2 * kChunk - 1; t >= kChunk; --t)
+                        filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
                 }
 #pragma unroll
-                for (int t = kChunk - 1; t >= 0; --t) {
-                    ma = __builtin_amdgcn_alignbit(ma, F::test(qk[t], wa, neg), 31);
-                    mb = __builtin_amdgcn_alignbit(mb, F::test(qk[t], wb, neg), 31);
-                }
+                for (int t = kChunk - 1; t >= 0; --t)
+                    filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
                 // bit t <-> query j0 + t; drop the padding queries
                 // and the lanes past the slab (only on the item's ragged edges)
                 if (nqc < 2u * kChunk || e0 + 128 > it.de) {
@@ -870,6 +1021,12 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k
             return hipErrorInvalidValue;
         return k == 1 ? launch_kmk<kPos32, 0, 1>(a, persistent, persistent_blocks, host_items, s)
                       : launch_kmk<kPos32, 0, 2>(a, persistent, persistent_blocks, host_items, s);
+    case kTherm32:
+        return launch_kind<kTherm32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kAsym32:
+        return launch_kind<kAsym32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kAsym64:
+        return launch_kind<kAsym64>(a, metric, k, persistent, persistent_blocks, host_items, s);
     default:
         return launch_kind<kAll>(a, metric, k, persistent, persistent_blocks, host_items, s);
     }

@@ -28,6 +28,8 @@ FPM_SCHED_PLAIN, FPM_SCHED_BATCHED, FPM_SCHED_BRUTE = 0, 1, 2
 VARIANTS = {"occ": FPM_OCC, "count": FPM_COUNT, "pos": FPM_POS, "occh": FPM_OCCH}
 METRICS = {"ham": FPM_HAM, "lev": FPM_LEV}
 SYMBOLS = {"common": FPM_COMMON, "rare": FPM_RARE, "mixed": FPM_MIXED, "custom": FPM_CUSTOM}
+FPM_BOUND_FD, FPM_BOUND_ASYM = 0, 1
+BOUNDS = {"fd": FPM_BOUND_FD, "asym": FPM_BOUND_ASYM}
 
 # every symbol include/fpm.h declares
 EXPORTS = [
@@ -63,7 +65,8 @@ class Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("queries_per_item", ctypes.c_uint32), ("slab", ctypes.c_uint32),
                 ("bucket_order", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
-                ("tail_split", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+                ("tail_split", ctypes.c_uint32), ("bound", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -92,6 +95,8 @@ def options(**kw) -> Options:
     for k, v in kw.items():
         if k not in names:
             raise TypeError(f"unknown option {k!r}")
+        if k == "bound":
+            v = _code(BOUNDS, v)
         setattr(o, k, v)
     return o
 

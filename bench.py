@@ -17,7 +17,11 @@ Forms timed on the same GPU:
                paper's naive comparison, giving its speedup S = T_n / T_f);
   learned      the batched form with the symbol grouping learned by the MLP
                (paper_1711_08475_amd/maps/<workload>_occ<bits>_k1.json, written by
-               `python -m paper_1711_08475_amd.learn`; --train retrains it here).
+               `python -m paper_1711_08475_amd.learn`; --train retrains it here);
+  asym         the learned form under the asymmetric bound (a filter rule
+               beyond the paper: both one-directional excesses <= k), with
+               popcount-ordered blocks and popcount-range tile skipping.
+The headline is the paper's rule (learned); asym is reported beside it.
 
 Prints one JSON line.  `value` is the headline form's logical pairs/s
 (|Q| * |D| / step time).
@@ -78,7 +82,7 @@ def load_traffic(form: str, workload: str):
     return t
 
 
-def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int):
+def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int, bound: str = "fd"):
     """Autotuner result for `key`, from the tuning table when present (so a
     profiled run dispatches the match kernel with one configuration only),
     else measured now and stored."""
@@ -88,10 +92,12 @@ def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k
     if key in table and not retune:
         return fpm.options(**table[key]), False
     t = time.perf_counter()
-    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2)
-    log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s")
+    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2,
+                                  base=fpm.options(bound=bound))
+    log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s; fastest (qt, slab, order, tail, ms): "
+        f"{sorted(rows, key=lambda r: r[4])[:4]}")
     entry = {k: v for k, v in best.as_dict().items()
-             if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split")}
+             if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split", "bound")}
     table[key] = entry
     with open(TUNING_FILE, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
@@ -153,8 +159,9 @@ def main():
     ap.add_argument("-k", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="plain,brute,learned",
-                    help="forms to time, from plain, batched, brute, learned; the last one named is the headline")
+    ap.add_argument("--modes", default="plain,brute,asym,learned",
+                    help="forms to time, from plain, batched, brute, asym, learned; the last one named is the "
+                         "headline")
     ap.add_argument("--train", action="store_true", help="train the learned grouping in this process")
     ap.add_argument("--no-autotune", action="store_true", help="default tiles for the batched form")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even when the table has an entry")
@@ -199,10 +206,9 @@ def main():
     modes = args.modes.split(",")
     results = {}
     hits = {}
-    tuned = None
     learned_meta = None
     indexes = {"paper": ix}
-    if "learned" in modes:
+    if "learned" in modes or "asym" in modes:
         from paper_1711_08475_amd import learn
 
         name = f"{args.workload}_{args.variant}{args.bits}_k{args.k}"
@@ -218,21 +224,22 @@ def main():
             opts = fpm.options(schedule=fpm.FPM_SCHED_PLAIN, time_kernel=1)
         elif mode == "brute":
             opts = fpm.options(schedule=fpm.FPM_SCHED_BRUTE, time_kernel=1)
-        elif mode in ("batched", "learned"):
-            mix = indexes["learned" if mode == "learned" else "paper"]
+        elif mode in ("batched", "learned", "asym"):
+            mix = indexes["paper" if mode == "batched" else "learned"]
+            bound = "asym" if mode == "asym" else "fd"
             if args.no_autotune:
-                opts = fpm.options(schedule=fpm.FPM_SCHED_BATCHED, time_kernel=1)
+                opts = fpm.options(schedule=fpm.FPM_SCHED_BATCHED, time_kernel=1, bound=bound)
             else:
                 key = (f"{args.workload}|{args.variant}{args.bits}|{args.metric}{args.k}|"
-                       f"{'learned' if mode == 'learned' else 'common'}")
-                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune, args.metric, args.k)
-                tuned = opts.as_dict()
-                log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {tuned}")
+                       f"{'common' if mode == 'batched' else 'learned'}" + ("|asym" if mode == "asym" else ""))
+                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune, args.metric, args.k,
+                                            bound)
+                log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {opts.as_dict()}")
                 opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
-        plan = fpm.fpm_plan_create(indexes["learned" if mode == "learned" else "paper"], nq, qbytes, args.metric,
-                                   args.k, opts)
+        plan = fpm.fpm_plan_create(indexes["paper" if mode in ("plain", "brute", "batched") else "learned"], nq,
+                                   qbytes, args.metric, args.k, opts)
         ms, n, st = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
         kms = fpm.fpm_plan_kernel_ms(plan, args.steps)
         results[mode] = {
@@ -240,6 +247,7 @@ def main():
             "pairs_per_s": nq * nd / (ms * 1e-3),
             "kernel_ms": float(np.mean(kms)) if kms.size else None,
             "stats": st,
+            "options": opts.as_dict(),
         }
         hits[mode] = fpm.fpm_plan_copy_matches(plan)
         log(f"{mode}: {ms:.3f} ms/step, kernel {results[mode]['kernel_ms']:.3f} ms, "
@@ -296,8 +304,9 @@ def main():
                         f"{'Levenshtein' if args.metric == 'lev' else 'Hamming'} k={args.k}",
             "fingerprint": f"{args.variant}{args.bits}",
             "form": head,
-            "symbols": "learned grouping" if head == "learned" else "common (paper map)",
-            "options": tuned,
+            "symbols": "learned grouping" if head in ("learned", "asym") else "common (paper map)",
+            "filter_rule": "asymmetric bound" if head == "asym" else "F_D <= 2k (Eq. 1)",
+            "options": r["options"],
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -98,7 +98,11 @@ struct StrSet {
     void *key = nullptr;
     uint32_t *fp_orig = nullptr;
     uint32_t *inv = nullptr;
-    uint32_t *ck = nullptr, *tmp_k = nullptr, *tmp_v = nullptr;  // (length, popcount) ordering
+    // popcount order inside the length blocks: the reordered strings,
+    // permutation and keys (the view then points at these)
+    uint32_t *str2 = nullptr, *perm2 = nullptr;
+    void *key2 = nullptr;
+    bool pop_ordered = false;
 
     hipError_t alloc(uint32_t max_n, uint64_t max_bytes, int kind, bool want_fp_orig, bool want_inv,
                      bool want_pop_order)
@@ -123,8 +127,12 @@ struct StrSet {
             return e;
         if (want_inv && (e = dalloc(&inv, max_n)))
             return e;
-        if (want_pop_order && ((e = dalloc(&ck, max_n)) || (e = dalloc(&tmp_k, max_n)) || (e = dalloc(&tmp_v, max_n))))
-            return e;
+        if (want_pop_order) {
+            const size_t kb = ((size_t)max_n + 64) * key_bytes(kind);
+            if ((e = dalloc(&str2, str_cap)) || (e = dalloc(&perm2, max_n)) || (e = dalloc((uint8_t **)&key2, kb)) ||
+                (e = hipMemset(str2, 0, str_cap * sizeof(uint32_t))) || (e = hipMemset(key2, 0, kb)))
+                return e;
+        }
         return hipSuccess;
     }
     void release()
@@ -139,17 +147,22 @@ struct StrSet {
         dfree(key);
         dfree(fp_orig);
         dfree(inv);
-        dfree(ck);
-        dfree(tmp_k);
-        dfree(tmp_v);
+        dfree(str2);
+        dfree(perm2);
+        dfree(key2);
     }
-    StrSetView view() const { return StrSetView{perm, slen, soff, str, off, key}; }
+    StrSetView view() const
+    {
+        if (pop_ordered)
+            return StrSetView{perm2, slen, soff, str2, off, key2};
+        return StrSetView{perm, slen, soff, str, off, key};
+    }
 };
 
 // Length sort, padded layout and fingerprints of n device strings.  With
-// pop_order (needs the StrSet's ordering buffers) each length block is
-// further ordered by the popcount of the filter key: the first layout only
-// yields those popcounts, the set is then laid out again in the final order.
+// pop_order (needs the StrSet's ordering buffers) each length block is then
+// ordered by the popcount of the filter key into the second buffers, which
+// the set's view returns from then on.
 void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, uint32_t n, uint64_t nbytes_limit,
                   const uint8_t *d_map, int variant, uint32_t bits, int kind, bool fingerprints, bool pop_order,
                   uint32_t *err, uint32_t *scratch, hipStream_t s)
@@ -161,16 +174,11 @@ void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, 
                   err, s);
     if (!fingerprints)
         return;
-    if (pop_order) {
-        launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, nullptr, S.key, kind,
-                            s);
-        launch_len_pop_keys(S.perm, S.slen, S.key, kind, n, S.ck, s);
-        launch_len_pop_sort(S.ck, n, S.perm, S.off, S.bdw, S.tmp_k, S.tmp_v, scratch, s);
-        launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str,
-                      S.str_cap, err, s);
-    }
     launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, S.fp_orig, S.key, kind,
                         s);
+    S.pop_ordered = pop_order;
+    if (pop_order)
+        launch_pop_order(S.off, S.bdw, S.str, S.perm, S.key, kind, S.str2, S.perm2, S.key2, s);
 }
 
 struct DevCounters {
@@ -558,34 +566,19 @@ static fpm_status build_asym_dictionary(fpm_plan *p)
     const StrSet &W = ix->words;
     const uint32_t n = ix->n;
     hipStream_t s = p->stream;
-    uint32_t *ck = nullptr, *src = nullptr, *tk = nullptr, *tv = nullptr, *off = nullptr, *bdw = nullptr;
-    auto cleanup = [&]() {
-        dfree(ck);
-        dfree(src);
-        dfree(tk);
-        dfree(tv);
-        dfree(off);
-        dfree(bdw);
-    };
-    const size_t kb = ((size_t)n + 64) * key_bytes(p->kind);
+    const size_t kb = ((size_t)n + 64) * key_bytes(p->kind);  // same width as the index's keys
     hipError_t e;
     if ((e = dalloc(&p->a_perm, std::max<uint32_t>(n, 1))) || (e = dalloc(&p->a_str, W.str_cap)) ||
-        (e = dalloc((uint8_t **)&p->a_key, kb)) || (e = dalloc(&ck, std::max<uint32_t>(n, 1))) ||
-        (e = dalloc(&src, std::max<uint32_t>(n, 1))) || (e = dalloc(&tk, std::max<uint32_t>(n, 1))) ||
-        (e = dalloc(&tv, std::max<uint32_t>(n, 1))) || (e = dalloc(&off, 257)) || (e = dalloc(&bdw, 257)) ||
-        (e = hipMemsetAsync(p->a_str, 0, W.str_cap * sizeof(uint32_t), s)) || (e = hipMemsetAsync(p->a_key, 0, kb, s))) {
-        cleanup();
+        (e = dalloc((uint8_t **)&p->a_key, kb)) ||
+        (e = hipMemsetAsync(p->a_str, 0, W.str_cap * sizeof(uint32_t), s)) || (e = hipMemsetAsync(p->a_key, 0, kb, s)))
         return hip_fail(e, "asymmetric-bound dictionary alloc");
-    }
-    launch_len_pop_keys(nullptr, W.slen, W.key, ix->kind, n, ck, s);
-    launch_len_pop_sort(ck, n, src, off, bdw, tk, tv, p->scratch, s);
-    launch_gather_slots(src, W.perm, W.slen, W.soff, W.str, n, p->a_str, p->a_perm, s);
-    launch_fingerprints(p->a_str, W.soff, W.slen, p->a_perm, n, ix->d_map, ix->variant, (int)ix->bits, nullptr,
-                        nullptr, p->a_key, p->kind, s);
+    launch_pop_order(W.off, W.bdw, W.str, W.perm, W.key, ix->kind, p->a_str, p->a_perm, p->a_key, s);
+    if (p->kind == kTherm32)  // the moved keys are the plain ones: extend them
+        launch_fingerprints(p->a_str, W.soff, W.slen, p->a_perm, n, ix->d_map, ix->variant, (int)ix->bits, nullptr,
+                            nullptr, p->a_key, p->kind, s);
     e = hipStreamSynchronize(s);
     if (!e)
         e = hipGetLastError();
-    cleanup();
     if (e)
         return hip_fail(e, "asymmetric-bound dictionary");
     return FPM_OK;
@@ -641,6 +634,7 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         plan_free(p);
         return hip_fail(e, "fpm_plan_create alloc");
     }
+    p->q.pop_ordered = p->asym;
     st = p->alloc_output(p->opt.match_capacity);
     if (!st && p->asym)
         st = build_asym_dictionary(p);

@@ -224,36 +224,99 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
     }
 }
 
-__global__ void k_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
-                               uint32_t *ck)
-{
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n)
-        return;
-    uint32_t pop;
-    if (key_is_64(key_kind))
-        pop = (uint32_t)__popcll(((const uint64_t *)keys)[p]);
-    else
-        pop = (uint32_t)__builtin_popcount(((const uint32_t *)keys)[p]);
-    ck[perm ? perm[p] : p] = ((uint32_t)slen[p] << 8) | pop;
-}
+// Reorder a laid-out set inside its length blocks by key popcount (stable):
+// one block of kOrderWaves waves per length L, each wave owning a contiguous
+// part of the length block.  Pass 1 counts each part's popcounts in LDS; the
+// counts are turned into each wave's first destination per popcount; pass 2
+// walks each part 64 positions at a time, ranks a lane among the lanes of
+// equal popcount with 7 ballots, and moves the padded string (the slot size
+// is uniform in a block), the caller index and the key to the new position.
+// Popcounts are at most 64.
+constexpr int kOrderWaves = 16;
 
-// Reorder a laid-out set inside its length blocks: new position p takes the
-// string at old position src[p] (same block, so same slot size; slot
-// offsets and lengths are per position and stay as they are).
-__global__ void k_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
-                               const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out)
+__global__ void __launch_bounds__(64 * kOrderWaves) k_pop_order(const uint32_t *off, const uint32_t *bdw,
+                                                                const uint32_t *str, const uint32_t *perm,
+                                                                const void *keys, int key_kind, uint32_t *str_out,
+                                                                uint32_t *perm_out, void *keys_out)
 {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n)
+    __shared__ uint32_t run[kOrderWaves][65];
+    __shared__ uint32_t base[65];
+    const uint32_t L = blockIdx.x, lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t s = off[L], e = off[L + 1];
+    if (s == e)
         return;
-    const uint32_t o = src[p];
-    const uint32_t sw = slot_dwords(slen[p]);
-    const uint32_t *in = str + soff[o];
-    uint32_t *out = str_out + soff[p];
-    for (uint32_t t = 0; t < sw; ++t)
-        out[t] = in[t];
-    perm_out[p] = perm[o];
+    const bool wide = key_is_64(key_kind);
+    const uint64_t *k64 = (const uint64_t *)keys;
+    const uint32_t *k32 = (const uint32_t *)keys;
+    for (uint32_t i = threadIdx.x; i < kOrderWaves * 65; i += blockDim.x)
+        (&run[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t lo = s + (uint32_t)((uint64_t)(e - s) * w / kOrderWaves);
+    const uint32_t hi = s + (uint32_t)((uint64_t)(e - s) * (w + 1) / kOrderWaves);
+    for (uint32_t i = lo + lane; i < hi; i += 64)
+        atomicAdd(&run[w][wide ? __popcll(k64[i]) : __builtin_popcount(k32[i])], 1u);
+    __syncthreads();
+    if (threadIdx.x < 65) {
+        uint32_t t = 0;
+        for (int ww = 0; ww < kOrderWaves; ++ww)
+            t += run[ww][threadIdx.x];
+        base[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = s;
+        for (int b = 0; b < 65; ++b) {
+            const uint32_t c = base[b];
+            base[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 65) {
+        uint32_t acc = base[threadIdx.x];
+        for (int ww = 0; ww < kOrderWaves; ++ww) {
+            const uint32_t c = run[ww][threadIdx.x];
+            run[ww][threadIdx.x] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    const uint32_t sw = slot_dwords(L);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *running = run[w];
+    for (uint32_t c0 = lo; c0 < hi; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        const bool active = i < hi;
+        uint64_t kv = 0;
+        if (active)
+            kv = wide ? k64[i] : k32[i];
+        const uint32_t pop = (uint32_t)__popcll(kv);
+        uint64_t peers = __ballot(active);
+#pragma unroll
+        for (int bit = 0; bit < 7; ++bit) {
+            const bool set = (pop >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t start = running[pop];
+        __builtin_amdgcn_wave_barrier();
+        if (active) {
+            const uint32_t rank = (uint32_t)__popcll(peers & below);
+            const uint32_t np = start + rank;
+            const uint32_t *in = str + bdw[L] + (i - s) * sw;
+            uint32_t *out = str_out + bdw[L] + (np - s) * sw;
+            for (uint32_t t = 0; t < sw; ++t)
+                out[t] = in[t];
+            perm_out[np] = perm[i];
+            if (wide)
+                ((uint64_t *)keys_out)[np] = kv;
+            else
+                ((uint32_t *)keys_out)[np] = (uint32_t)kv;
+            if (rank == 0)
+                running[pop] = start + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 __global__ void k_invert(const uint32_t *perm, uint32_t n, uint32_t *inv)
@@ -330,21 +393,12 @@ void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_
     }
 }
 
-void launch_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
-                         uint32_t *ck, hipStream_t s)
+void launch_pop_order(const uint32_t *off, const uint32_t *bdw, const uint32_t *str, const uint32_t *perm,
+                      const void *keys, int key_kind, uint32_t *str_out, uint32_t *perm_out, void *keys_out,
+                      hipStream_t s)
 {
-    if (n == 0)
-        return;
-    hipLaunchKernelGGL(k_len_pop_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, slen, keys, key_kind, n, ck);
-}
-
-void launch_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
-                         const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out, hipStream_t s)
-{
-    if (n == 0)
-        return;
-    hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, perm, slen, soff, str, n,
-                       str_out, perm_out);
+    hipLaunchKernelGGL(k_pop_order, dim3(256), dim3(64 * kOrderWaves), 0, s, off, bdw, str, perm, keys, key_kind,
+                       str_out, perm_out, keys_out);
 }
 
 void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t s)

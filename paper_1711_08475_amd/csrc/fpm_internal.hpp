@@ -105,23 +105,13 @@ void launch_byte_histogram(const uint8_t *bytes, const uint64_t *offsets, uint32
 // Symbol map from a histogram (common / rare / mixed), map_out[256].
 void launch_select_symbols(const unsigned long long *hist, int nfields, int symset, uint8_t *map_out, hipStream_t s);
 
-// Composite sort keys (length << 8 | key popcount) from the keys of a
-// length-sorted set: ck[perm[p]] for sorted position p (caller order), or
-// ck[p] when perm is null (position order).
-void launch_len_pop_keys(const uint32_t *perm, const uint8_t *slen, const void *keys, int key_kind, uint32_t n,
-                         uint32_t *ck, hipStream_t s);
-
-// Reorder a laid-out set inside its length blocks: position p of the output
-// takes the padded string and caller index of old position src[p] (src
-// must map each block onto itself).  Lengths and slot offsets are shared.
-void launch_gather_slots(const uint32_t *src, const uint32_t *perm, const uint8_t *slen, const uint32_t *soff,
-                         const uint32_t *str, uint32_t n, uint32_t *str_out, uint32_t *perm_out, hipStream_t s);
-
-// Stable sort of indices 0..n-1 by (length, popcount) from composite keys
-// (two 8-bit radix passes); same outputs as launch_length_sort.  tmp_k and
-// tmp_v: n uint32 each.
-void launch_len_pop_sort(const uint32_t *ck, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
-                         uint32_t *tmp_k, uint32_t *tmp_v, uint32_t *scratch, hipStream_t s);
+// Reorder a laid-out set (block tables off / bdw, padded strings, sorted ->
+// caller perm, keys of key_kind) inside each length block by key popcount,
+// stably, into str_out / perm_out / keys_out (slot offsets and lengths are
+// per position and stay valid).  One launch, one block per length.
+void launch_pop_order(const uint32_t *off, const uint32_t *bdw, const uint32_t *str, const uint32_t *perm,
+                      const void *keys, int key_kind, uint32_t *str_out, uint32_t *perm_out, void *keys_out,
+                      hipStream_t s);
 
 // Stable sort of indices 0..n-1 by length (a single 8-bit radix pass).
 // Writes perm (sorted -> caller index), off[257] bucket offsets and

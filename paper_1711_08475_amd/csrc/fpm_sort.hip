@@ -258,16 +258,6 @@ void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_
     hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
 }
 
-void launch_len_pop_sort(const uint32_t *ck, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
-                         uint32_t *tmp_k, uint32_t *tmp_v, uint32_t *scratch, hipStream_t s)
-{
-    // least significant digit (popcount) first; the length pass is stable,
-    // so each length block keeps ascending popcounts
-    radix_pass<uint32_t>(ck, nullptr, tmp_k, tmp_v, nullptr, n, n, 0, scratch, s);
-    radix_pass<uint32_t>(tmp_k, tmp_v, nullptr, perm, nullptr, n, n, 8, scratch, s);
-    hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
-}
-
 const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
                                  uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
 {

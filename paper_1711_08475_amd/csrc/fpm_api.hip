@@ -113,9 +113,10 @@ struct StrSet {
         if ((e = dalloc(&len, max_n)) || (e = dalloc(&perm, max_n)) || (e = dalloc(&soff, max_n)) ||
             (e = dalloc(&slen, max_n)) || (e = dalloc(&off, 257)) || (e = dalloc(&bdw, 257)))
             return e;
-        // padded strings: a slot holds at most L/4 + 3 dwords and at most 64,
-        // each of the 256 length blocks adds at most 3 dwords of alignment
-        str_cap = std::min<uint64_t>(max_bytes / 4 + 3ull * max_n, (uint64_t)max_n * 64) + 1024 + 16;
+        // padded strings: a slot of L bytes holds at most L/4 + 3.75 dwords
+        // (L = 17: 8 dwords) and at most 64; each of the 256 length blocks
+        // adds at most 3 dwords of alignment
+        str_cap = std::min<uint64_t>(max_bytes / 4 + 4ull * max_n, (uint64_t)max_n * 64) + 1024 + 16;
         if ((e = dalloc(&str, str_cap)))
             return e;
         // keys carry one filter chunk of padding (read, never used)
@@ -431,8 +432,10 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     prep_strings(ix->words, d_bytes, d_off, n_words, nbytes, ix->d_map, variant, bits, ix->kind, true, false, d_err,
                  scratch, s);
     launch_invert(ix->words.perm, n_words, ix->words.inv, s);
+    uint32_t h_err = 0;
     (void)hipMemcpyAsync(ix->map, ix->d_map, 256, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(ix->h_off, ix->words.off, sizeof(uint32_t) * 257, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&h_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     e = hipStreamSynchronize(s);
     if (!e)
         e = hipGetLastError();
@@ -440,6 +443,10 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     if (e) {
         fpm_index_destroy(ix);
         return hip_fail(e, "fpm_build_fingerprints");
+    }
+    if (h_err) {  // the host checks above leave only a layout overflow
+        fpm_index_destroy(ix);
+        return fail(FPM_EDEVICE, "fpm_build_fingerprints: padded layout failed (flags %u)", h_err);
     }
     *out = ix;
     return FPM_OK;
@@ -1030,6 +1037,12 @@ struct TmpSet {
         launch_zero(err, 1, s);
         prep_strings(S, b, o, n, nbytes, ix->d_map, ix->variant, ix->bits, ix->kind, true, false, err, scratch, s);
         launch_invert(S.perm, n, S.inv, s);
+        uint32_t h_err = 0;
+        if ((e = hipMemcpyAsync(&h_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) ||
+            (e = hipStreamSynchronize(s)))
+            return hip_fail(e, "temporary string set");
+        if (h_err)  // the host checks leave only a layout overflow
+            return fail(FPM_EDEVICE, "temporary string set: padded layout failed (flags %u)", h_err);
         return FPM_OK;
     }
 };

@@ -367,3 +367,26 @@ def test_full_size_sampled_parity(fpm, name, bits, metric, k):
     got = res[fpm.FPM_SCHED_BATCHED]
     got = got[np.isin(got[:, 0], sample)]
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("length", [1, 5, 17, 33, 49, 241])
+def test_single_length_layout_capacity(fpm, length):
+    """Every word and query of one length L with L = 1 (mod 16) or 1 (mod 4):
+    the padded slots are then widest relative to the bytes (L = 17: 8 dwords
+    for 17 bytes), which the string buffers must hold for every word."""
+    d, q = datagen.fixed_length_workload(3000, 120, length, 77 + length)
+    say("single length", length)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 32, "common")
+    m = fpm.fpm_get_map(ix)
+    assert np.array_equal(fpm.fpm_get_fingerprints(ix), oracle.fingerprints(d, oracle.OCC, 32, m))
+    assert np.array_equal(fpm.fpm_fingerprints(ix, q), oracle.fingerprints(q, oracle.OCC, 32, m))
+    for metric, k in [(oracle.HAM, 1), (oracle.LEV, 2)] if length < 64 else [(oracle.HAM, 1)]:
+        ref = oracle.match(d, q, metric, k)
+        for sched in (0, 1, 2):
+            got = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched))
+            assert np.array_equal(got, ref)
+    # exact distances of every (query, last words) pair through the verifier
+    pairs = np.array([[i, j] for i in range(0, 120, 7) for j in range(2990, 3000)], dtype=np.uint32)
+    dist = fpm.fpm_verify_pairs(ix, q, pairs, "ham", 1)
+    ref = oracle.pair_dist(d, q, pairs, oracle.HAM)
+    assert np.array_equal(dist, np.minimum(ref, 2))

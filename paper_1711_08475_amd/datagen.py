@@ -91,6 +91,8 @@ def english_lengths(rng, n: int, law: str) -> np.ndarray:
         return 3 + rng.binomial(12, 1.0 / 3.0, size=n)
     if law == "2-20":  # 2 + Binomial(18, 5/18): 2..20, mode 7
         return 2 + rng.binomial(18, 5.0 / 18.0, size=n)
+    if law.startswith("fixed:"):  # every word of one length
+        return np.full(n, int(law[6:]), dtype=np.int64)
     raise ValueError(law)
 
 
@@ -235,6 +237,33 @@ def english_workload(n_words: int, n_queries: int, seed: int, law: str, rho: flo
 
     q = make_queries(d, n_queries, qs, rho, edit_choices, fresh, alpha.draw, min_len=2 if law == "2-20" else 3)
     return d, q
+
+
+def fixed_length_workload(n_words: int, n_queries: int, length: int, seed: int, rho: float = 0.5):
+    """English-like words of one length (the single-length dictionaries of
+    the paper's word-size experiment) and queries of the same length: with
+    probability ``rho`` a dictionary word with one substitution, else a fresh
+    word."""
+    alpha = EnglishLike(seed)
+    law = f"fixed:{length}"
+    d = english_words(n_words, seed, law, alpha)
+    rng = np.random.default_rng([seed, 0x5F, length])
+    raw, offs = d[0], d[1]
+    fresh = english_words(n_queries, seed + 7919, law, alpha)[0].reshape(n_queries, length) if length else None
+    out = []
+    for i in range(n_queries):
+        if length and rng.random() < rho:
+            j = int(rng.integers(n_words))
+            w = bytearray(raw[int(offs[j]):int(offs[j + 1])].tobytes())
+            pos = int(rng.integers(length))
+            c = int(alpha.draw(rng, 1)[0])
+            while c == w[pos]:
+                c = int(alpha.draw(rng, 1)[0])
+            w[pos] = c
+            out.append(bytes(w))
+        else:
+            out.append(fresh[i].tobytes() if length else b"")
+    return d, to_csr(out)
 
 
 def url_workload(n_words: int, n_queries: int, seed: int, rho: float = 0.3, edit_choices=(1, 2),

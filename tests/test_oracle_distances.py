@@ -204,3 +204,15 @@ def test_match_k_monotone_and_ham_subset():
 def test_rejects_overlong_strings():
     with pytest.raises(ValueError):
         oracle.match([b"a" * 256], [b"a"], oracle.LEV, 1)
+
+
+def test_fixed_length_workload_shape():
+    """Single-length words and queries; about half of the queries are one
+    substitution away from a dictionary word, so Ham k = 1 finds them."""
+    from paper_1711_08475_amd import datagen
+
+    d, q = datagen.fixed_length_workload(3000, 200, 9, 5)
+    assert set(datagen.csr_lengths(d)) == {9} and set(datagen.csr_lengths(q)) == {9}
+    hits = oracle.match(d, q, oracle.HAM, 1)
+    near = np.unique(hits[hits[:, 2] == 1, 0]).size
+    assert 70 <= near <= 130

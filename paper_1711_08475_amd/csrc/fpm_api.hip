@@ -412,7 +412,7 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&d_bytes, nbytes + 4)) ||
         (e = dalloc(&d_off, (size_t)n_words + 1)) || (e = dalloc(&d_hist, 256)) ||
-        (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&d_err, 1)) || (e = dalloc(&ix->d_map, 256)) ||
+        (e = dalloc(&scratch, kRadixScratch)) || (e = dalloc(&d_err, 1)) || (e = dalloc(&ix->d_map, 256)) ||
         (e = ix->words.alloc(n_words, nbytes, ix->kind, true, true, false))) {
         cleanup();
         fpm_index_destroy(ix);
@@ -636,7 +636,7 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     }
     const int qkind = p->kind == kAll ? kPop32 : p->kind;
     if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false, p->asym)) ||
-        (e = dalloc(&p->scratch, 256u * kRadixBlocks)) || (e = dalloc(&p->pairs, kMaxPairs)) ||
+        (e = dalloc(&p->scratch, kRadixScratch)) || (e = dalloc(&p->pairs, kMaxPairs)) ||
         (e = dalloc(&p->ctr, 1)) || (e = hipEventCreate(&p->ev0)) || (e = hipEventCreate(&p->ev1))) {
         plan_free(p);
         return hip_fail(e, "fpm_plan_create alloc");
@@ -1028,7 +1028,7 @@ struct TmpSet {
         const uint64_t nbytes = offsets[n];
         hipError_t e;
         if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&b, nbytes + 4)) ||
-            (e = dalloc(&o, (size_t)n + 1)) || (e = dalloc(&scratch, 256u * kRadixBlocks)) || (e = dalloc(&err, 1)) ||
+            (e = dalloc(&o, (size_t)n + 1)) || (e = dalloc(&scratch, kRadixScratch)) || (e = dalloc(&err, 1)) ||
             (e = S.alloc(n, nbytes + 4, ix->kind, fp_orig, true, false)))
             return hip_fail(e, "temporary string set");
         if (nbytes)

@@ -23,7 +23,12 @@ namespace fpm {
 constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
 constexpr int kMaxPairs = 2 * 256 * 5;  // (query length, word length) pairs, |dL| <= 2, full + tail part
-constexpr int kRadixBlocks = 128;    // blocks of one stable radix pass (16 waves each)
+constexpr int kRadixShift = 7;
+constexpr int kRadixBlocks = 1 << kRadixShift;  // blocks of one stable radix pass (16 waves each)
+constexpr int kSortBits = 9;                    // digit width of the match-list sort (lengths use 8)
+// uint32 scratch of a pass: the digit table [bins][kRadixBlocks], then the
+// bins' totals
+constexpr size_t kRadixScratch = ((size_t)kRadixBlocks << kSortBits) + (1u << kSortBits);
 
 __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 {
@@ -115,7 +120,7 @@ void launch_pop_order(const uint32_t *off, const uint32_t *bdw, const uint32_t *
 
 // Stable sort of indices 0..n-1 by length (a single 8-bit radix pass).
 // Writes perm (sorted -> caller index), off[257] bucket offsets and
-// bdw[257] dword offsets of the padded blocks.  scratch: 256*kRadixBlocks
+// bdw[257] dword offsets of the padded blocks.  scratch: kRadixScratch
 // uint32.
 void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
                         uint32_t *scratch, hipStream_t s);
@@ -165,9 +170,9 @@ void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t 
 
 // ----------------------------------------------------------------- sort
 // Stable LSD radix sort of n64 keys (count read from device) on bits
-// [lo_bit, hi_bit); ping-pongs between keys and tmp and returns the buffer
-// that holds the result (keys for an even pass count, else tmp).  scratch:
-// 256*kRadixBlocks uint32.
+// [lo_bit, hi_bit), kSortBits per pass; ping-pongs between keys and tmp and
+// returns the buffer that holds the result (keys for an even pass count,
+// else tmp).  scratch: kRadixScratch uint32.
 const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
                                  uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s);
 // Packed keys -> fpm_match triples (count read from device, clamped to cap).

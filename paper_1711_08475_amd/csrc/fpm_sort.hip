@@ -1,17 +1,19 @@
-// fpm_sort.hip -- stable LSD radix sort passes (8-bit digits) used for the
-// length bucketing of dictionaries and query batches and for the final
-// (query, word) ordering of the match list.
+// fpm_sort.hip -- stable LSD radix sort passes used for the length bucketing
+// of dictionaries and query batches (8-bit digits) and for the final
+// (query, word) ordering of the match list (kSortBits-bit digits).
 //
 // One pass = three launches:
 //   hist:    kRadixBlocks blocks each count the digits of a contiguous range;
-//   scan:    one block turns the digit-major table [256][kRadixBlocks] into
-//            exclusive offsets, so block b's first item of digit d goes to
-//            offs[d][b];
+//   scan:    one wave per digit row of the digit-major table
+//            [bins][kRadixBlocks] turns it into exclusive offsets within the
+//            row and writes the digit's total; the scatter adds the totals of
+//            the smaller digits, so block b's first item of digit d goes to
+//            sum(totals[< d]) + offs[d][b];
 //   scatter: each block splits its range into kScatterWaves contiguous
 //            sub-ranges, counts their digits in LDS, derives each wave's
 //            starting offsets, and every wave walks its sub-range in order,
-//            64 items at a time; lanes with equal digits are found with 8
-//            ballots, so the rank of a lane among equal digits is the
+//            64 items at a time; lanes with equal digits are found with one
+//            ballot per digit bit, so the rank of a lane among equal digits is the
 //            popcount of its peers below it -- the pass is stable.
 // The item count may live in device memory (match list), so every kernel
 // splits [0, n) into kRadixBlocks ranges at run time.
@@ -29,13 +31,15 @@ __device__ __forceinline__ uint64_t range_n(const uint64_t *dcount, uint64_t hco
     return n < cap ? n : cap;
 }
 
-template <typename K>
+template <typename K, int BITS>
 __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_t *dcount, uint64_t hcount,
                                                     uint64_t cap, uint32_t shift, uint32_t *hist)
 {
-    __shared__ uint32_t h[256];
+    constexpr uint32_t BINS = 1u << BITS, MASK = BINS - 1u;
+    __shared__ uint32_t h[BINS];
     const uint32_t b = blockIdx.x;
-    h[threadIdx.x] = 0;
+    for (uint32_t d = threadIdx.x; d < BINS; d += 256)
+        h[d] = 0;
     __syncthreads();
     const uint64_t n = range_n(dcount, hcount, cap);
     const uint64_t lo = n * b / kRadixBlocks, hi = n * (b + 1) / kRadixBlocks;
@@ -45,15 +49,16 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *keys, const uint64_
         uint32_t d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            d[u] = (uint32_t)(keys[i + u * 256] >> shift) & 0xFFu;
+            d[u] = (uint32_t)(keys[i + u * 256] >> shift) & MASK;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             atomicAdd(&h[d[u]], 1u);
     }
     for (; i < hi; i += 256)
-        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 0xFFu], 1u);
+        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & MASK], 1u);
     __syncthreads();
-    hist[threadIdx.x * kRadixBlocks + b] = h[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < BINS; d += 256)
+        hist[d * kRadixBlocks + b] = h[d];
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave (shuffles).
@@ -68,87 +73,85 @@ __device__ __forceinline__ uint32_t wave_inclusive(uint32_t v, uint32_t lane)
     return v;
 }
 
-// Exclusive scan of the digit-major table [256][kRadixBlocks] in place, one
-// block of 16 waves.  Wave w owns digit rows 16w .. 16w+15; a row is read
-// and written coalesced (kRadixBlocks / 64 consecutive entries per lane) and
-// scanned with shuffles; one wave then scans the 256 row totals.
-__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *v)
+// Row scans of the digit-major table [BINS][kRadixBlocks]: one wave per
+// digit row (kRadixBlocks / 64 entries per lane, read and written
+// coalesced) turns the row into exclusive offsets within the row and writes
+// the row total (the digit's count) to totals[digit].  Rows are independent,
+// so the pass spreads over BINS / 16 blocks; the offsets of the rows before
+// a digit are added where they are used (scatter, bucket tables).
+__global__ void __launch_bounds__(1024) k_scan_rows(uint32_t *v, uint32_t *totals)
 {
     constexpr int PL = kRadixBlocks / 64;  // entries per lane and row
     static_assert(kRadixBlocks % 64 == 0, "rows are split evenly over the lanes");
-    __shared__ uint32_t rowbase[256];
-    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    uint32_t x[16][PL], ex[16];
+    const uint32_t lane = threadIdx.x & 63u, row = blockIdx.x * 16u + (threadIdx.x >> 6);
+    uint32_t *r = v + (size_t)row * kRadixBlocks + lane * PL;
+    uint32_t x[PL], sum = 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int e = 0; e < PL; ++e) {
+        x[e] = r[e];
+        sum += x[e];
+    }
+    const uint32_t inc = wave_inclusive(sum, lane);
+    uint32_t run = inc - sum;
 #pragma unroll
-        for (int e = 0; e < PL; ++e)
-            x[r][e] = v[(16 * w + r) * kRadixBlocks + lane * PL + e];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        uint32_t sum = 0;
-#pragma unroll
-        for (int e = 0; e < PL; ++e)
-            sum += x[r][e];
-        const uint32_t inc = wave_inclusive(sum, lane);
-        ex[r] = inc - sum;
-        if (lane == 63)
-            rowbase[16 * w + r] = inc;  // row total for now
+    for (int e = 0; e < PL; ++e) {
+        r[e] = run;
+        run += x[e];
+    }
+    if (lane == 63)
+        totals[row] = inc;
+}
+
+// Exclusive prefix over digits of the BINS row totals, into base[] (LDS), by
+// a block of at least BINS threads.  wsum: one LDS word per wave.
+template <int BINS>
+__device__ __forceinline__ void digit_bases(const uint32_t *totals, uint32_t *base, uint32_t *wsum)
+{
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t c = t < (uint32_t)BINS ? totals[t] : 0u;
+    const uint32_t inc = wave_inclusive(c, lane);
+    if (t < (uint32_t)BINS && lane == 63)
+        wsum[w] = inc;
+    __syncthreads();
+    if (t < (uint32_t)BINS) {
+        uint32_t ex = inc - c;
+        for (uint32_t j = 0; j < w; ++j)
+            ex += wsum[j];
+        base[t] = ex;
     }
     __syncthreads();
-    if (w == 0) {
-        uint32_t t[4], sum = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            t[e] = rowbase[4 * lane + e];
-            sum += t[e];
-        }
-        uint32_t run = wave_inclusive(sum, lane) - sum;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            rowbase[4 * lane + e] = run;
-            run += t[e];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        uint32_t run = rowbase[16 * w + r] + ex[r];
-#pragma unroll
-        for (int e = 0; e < PL; ++e) {
-            const uint32_t c = x[r][e];
-            v[(16 * w + r) * kRadixBlocks + lane * PL + e] = run;
-            run += c;
-        }
-    }
 }
 
 // kScatterWaves waves per block.  vals_in == nullptr means value = item index.
 constexpr int kScatterWaves = 16;
 
-template <typename K>
+template <typename K, int BITS>
 __global__ void __launch_bounds__(64 * kScatterWaves) k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
                                                                       K *keys_out, uint32_t *vals_out,
                                                                       const uint64_t *dcount, uint64_t hcount,
                                                                       uint64_t cap, uint32_t shift,
                                                                       const uint32_t *offs)
 {
-    __shared__ uint32_t run[kScatterWaves][256];
+    constexpr uint32_t BINS = 1u << BITS, MASK = BINS - 1u;
+    static_assert(BINS <= 64 * kScatterWaves, "one thread per digit in the prefix step");
+    __shared__ uint32_t run[kScatterWaves][BINS];
+    __shared__ uint32_t base[BINS];
+    __shared__ uint32_t wsum[kScatterWaves];
     const uint32_t b = blockIdx.x, lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    for (uint32_t i = threadIdx.x; i < kScatterWaves * 256; i += blockDim.x)
+    for (uint32_t i = threadIdx.x; i < kScatterWaves * BINS; i += blockDim.x)
         (&run[0][0])[i] = 0;
-    __syncthreads();
+    digit_bases<BINS>(offs + ((size_t)BINS << kRadixShift), base, wsum);
     const uint64_t n = range_n(dcount, hcount, cap);
     const uint64_t blo = n * b / kRadixBlocks, bhi = n * (b + 1) / kRadixBlocks;
     const uint64_t lo = blo + (bhi - blo) * w / kScatterWaves, hi = blo + (bhi - blo) * (w + 1) / kScatterWaves;
     // digit counts of each wave's sub-range
     for (uint64_t i = lo + lane; i < hi; i += 64)
-        atomicAdd(&run[w][(uint32_t)(keys_in[i] >> shift) & 0xFFu], 1u);
+        atomicAdd(&run[w][(uint32_t)(keys_in[i] >> shift) & MASK], 1u);
     __syncthreads();
     // exclusive prefix over the waves, starting at the block's offsets
-    if (threadIdx.x < 256) {
+    if (threadIdx.x < BINS) {
         const uint32_t d = threadIdx.x;
-        uint32_t r = offs[d * kRadixBlocks + b];
+        uint32_t r = base[d] + offs[d * kRadixBlocks + b];
         for (int ww = 0; ww < kScatterWaves; ++ww) {
             const uint32_t c = run[ww][d];
             run[ww][d] = r;
@@ -167,10 +170,10 @@ __global__ void __launch_bounds__(64 * kScatterWaves) k_radix_scatter(const K *k
         uint32_t val = 0;
         if (active)
             val = vals_in ? vals_in[i] : (uint32_t)i;
-        const uint32_t digit = (uint32_t)(key >> shift) & 0xFFu;
+        const uint32_t digit = (uint32_t)(key >> shift) & MASK;
         uint64_t peers = __ballot(active);
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
+        for (int bit = 0; bit < BITS; ++bit) {
             const bool set = (digit >> bit) & 1u;
             const uint64_t m = __ballot(set);
             peers &= set ? m : ~m;
@@ -198,13 +201,15 @@ __global__ void __launch_bounds__(256) k_bucket_tables(const uint32_t *offs, uin
                                                        uint32_t *bdw)
 {
     __shared__ uint32_t part[256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wsum[4];
     const uint32_t L = threadIdx.x;
-    const uint32_t start = offs[L * kRadixBlocks];
-    const uint32_t end = (L == 255) ? n : offs[(L + 1) * kRadixBlocks];
-    off[L] = start;
+    const uint32_t *counts = offs + ((size_t)256 << kRadixShift);  // row totals of the 8-bit length pass
+    digit_bases<256>(counts, base, wsum);
+    off[L] = base[L];
     if (L == 255)
         off[256] = n;
-    part[L] = ((end - start) * slot_dwords(L) + 3u) & ~3u;  // 16-byte aligned blocks
+    part[L] = (counts[L] * slot_dwords(L) + 3u) & ~3u;  // 16-byte aligned blocks
     __syncthreads();
     for (uint32_t o = 1; o < 256; o <<= 1) {
         uint32_t x = L >= o ? part[L - o] : 0;
@@ -238,14 +243,15 @@ __global__ void k_unpack(const uint64_t *keys, const uint64_t *dcount, uint64_t 
     }
 }
 
-template <typename K>
+template <typename K, int BITS>
 void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, const uint64_t *dcount, uint64_t hcount,
                 uint64_t cap, uint32_t shift, uint32_t *scratch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
+    hipLaunchKernelGGL((k_radix_hist<K, BITS>), dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
-    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, scratch);
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
+    hipLaunchKernelGGL(k_scan_rows, dim3((1 << BITS) / 16), dim3(1024), 0, s, scratch,
+                       scratch + ((size_t)(1 << BITS) << kRadixShift));
+    hipLaunchKernelGGL((k_radix_scatter<K, BITS>), dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
                        dcount, hcount, cap, shift, scratch);
 }
 
@@ -254,7 +260,7 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, cons
 void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_t *off, uint32_t *bdw,
                         uint32_t *scratch, hipStream_t s)
 {
-    radix_pass<uint32_t>(len, nullptr, nullptr, perm, nullptr, n, n, 0, scratch, s);
+    radix_pass<uint32_t, 8>(len, nullptr, nullptr, perm, nullptr, n, n, 0, scratch, s);
     hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
 }
 
@@ -262,8 +268,8 @@ const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *
                                  uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
 {
     uint64_t *a = keys, *b = tmp;
-    for (uint32_t shift = lo_bit; shift < hi_bit; shift += 8) {
-        radix_pass<uint64_t>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s);
+    for (uint32_t shift = lo_bit; shift < hi_bit; shift += kSortBits) {
+        radix_pass<uint64_t, kSortBits>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s);
         uint64_t *t = a;
         a = b;
         b = t;

@@ -171,13 +171,14 @@ void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, 
     S.n = n;
     launch_lengths(d_offsets, n, S.len, err, s);
     launch_length_sort(S.len, n, S.perm, S.off, S.bdw, scratch, s);
-    launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str, S.str_cap,
-                  err, s);
-    if (!fingerprints)
+    S.pop_ordered = fingerprints && pop_order;
+    if (!fingerprints) {
+        launch_layout(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str,
+                      S.str_cap, err, s);
         return;
-    launch_fingerprints(S.str, S.soff, S.slen, S.perm, n, d_map, variant, (int)bits, nullptr, S.fp_orig, S.key, kind,
-                        s);
-    S.pop_ordered = pop_order;
+    }
+    launch_layout_fp(d_bytes, d_offsets, nbytes_limit, S.perm, S.len, S.off, S.bdw, n, S.slen, S.soff, S.str,
+                     S.str_cap, err, d_map, variant, (int)bits, S.fp_orig, S.key, kind, s);
     if (pop_order)
         launch_pop_order(S.off, S.bdw, S.str, S.perm, S.key, kind, S.str2, S.perm2, S.key2, s);
 }
@@ -735,9 +736,8 @@ static void enqueue_post(fpm_plan *p, uint32_t nq)
 {
     const fpm_index *ix = p->ix;
     const uint32_t qbits = bits_for(std::max<uint32_t>(nq, 1));
-    const uint64_t *sorted =
-        launch_sort_keys(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, p->scratch, p->stream);
-    launch_unpack(sorted, &p->ctr->n_out, p->cap, ix->wbits, p->triples, p->survivors_only ? 1 : 0, p->stream);
+    launch_sort_unpack(p->keys, p->tmp, &p->ctr->n_out, p->cap, 2, 2 + ix->wbits + qbits, ix->wbits, p->triples,
+                       p->survivors_only ? 1 : 0, p->scratch, p->stream);
 }
 
 static fpm_status capture(fpm_plan *p, hipGraphExec_t *out, int part, const uint8_t *b, const uint64_t *o,

@@ -140,7 +140,8 @@ __global__ void k_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t
     }
 }
 
-// Fingerprint of one padded string (Section 3.2).  Field f of the map:
+// Fingerprint construction (Section 3.2), one dword (4 symbols) at a time.
+// Field f of the map:
 //   occ  -> bit f;
 //   occh -> bit 2f for a symbol in the first floor(L/2) positions, 2f+1 after;
 //   count-> 2-bit saturating counter at bits 2f, 2f+1;
@@ -148,41 +149,77 @@ __global__ void k_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t
 //           when it is >= 7 or the symbol is absent; f >= npos: occurrence
 //           bit 3*npos + (f - npos).
 template <int VARIANT>
-__device__ __forceinline__ uint32_t fingerprint(const uint32_t *s, uint32_t L, const uint8_t *smap, uint32_t npos)
+__device__ __forceinline__ uint32_t fp_init(uint32_t npos)
 {
-    uint32_t fp = 0;
     if (VARIANT == 2)
-        fp = (npos == 10) ? 0x3FFFFFFFu : 0x7FFFu;  // every position field starts at all ones
+        return (npos == 10) ? 0x3FFFFFFFu : 0x7FFFu;  // every position field starts at all ones
+    return 0;
+}
+
+// Symbols 4t .. 4t+3 of a string of length L (held in w, first symbol in the
+// low byte) into fp.
+template <int VARIANT>
+__device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t w, uint32_t t, uint32_t L, const uint8_t *smap,
+                                         uint32_t npos)
+{
     const uint32_t half = L >> 1;
-    const uint32_t nw = (L + 3) >> 2;
-    for (uint32_t t = 0; t < nw; ++t) {
-        const uint32_t w = s[t];
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) {
-            const uint32_t pos = 4 * t + j;
-            if (pos >= L)
-                break;
-            const uint32_t f = smap[(w >> (8 * j)) & 0xFFu];
-            if (f == 0xFFu)
-                continue;
-            if (VARIANT == 0) {
-                fp |= 1u << f;
-            } else if (VARIANT == 3) {
-                fp |= 1u << (2 * f + (pos >= half ? 1u : 0u));
-            } else if (VARIANT == 1) {
-                if (((fp >> (2 * f)) & 3u) != 3u)
-                    fp += 1u << (2 * f);
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t pos = 4 * t + j;
+        if (pos >= L)
+            break;
+        const uint32_t f = smap[(w >> (8 * j)) & 0xFFu];
+        if (f == 0xFFu)
+            continue;
+        if (VARIANT == 0) {
+            fp |= 1u << f;
+        } else if (VARIANT == 3) {
+            fp |= 1u << (2 * f + (pos >= half ? 1u : 0u));
+        } else if (VARIANT == 1) {
+            if (((fp >> (2 * f)) & 3u) != 3u)
+                fp += 1u << (2 * f);
+        } else {
+            if (f < npos) {
+                if (pos < 7 && ((fp >> (3 * f)) & 7u) == 7u)
+                    fp = (fp & ~(7u << (3 * f))) | (pos << (3 * f));
             } else {
-                if (f < npos) {
-                    if (pos < 7 && ((fp >> (3 * f)) & 7u) == 7u)
-                        fp = (fp & ~(7u << (3 * f))) | (pos << (3 * f));
-                } else {
-                    fp |= 1u << (3 * npos + (f - npos));
-                }
+                fp |= 1u << (3 * npos + (f - npos));
             }
         }
     }
+}
+
+template <int VARIANT>
+__device__ __forceinline__ uint32_t fingerprint(const uint32_t *s, uint32_t L, const uint8_t *smap, uint32_t npos)
+{
+    uint32_t fp = fp_init<VARIANT>(npos);
+    const uint32_t nw = (L + 3) >> 2;
+    for (uint32_t t = 0; t < nw; ++t)
+        fp_dword<VARIANT>(fp, s[t], t, L, smap, npos);
     return fp;
+}
+
+// Filter key of a fingerprint at sorted position p.
+template <int VARIANT>
+__device__ __forceinline__ void store_key(uint32_t fp, int key_kind, void *keys, uint32_t p)
+{
+    if (VARIANT == 1) {
+        // thermometer expansion of each 2-bit count v: [v>=1, v>=2, v>=3];
+        // the popcount of the XOR of two expansions is the L1 distance of
+        // the counts.
+        const uint32_t lo = fp & 0x55555555u, hi = (fp >> 1) & 0x55555555u;
+        const uint32_t t0 = lo | hi, t1 = hi, t2 = lo & hi;
+        if (key_is_64(key_kind)) {
+            ((uint64_t *)keys)[p] = (uint64_t)(t0 | (t1 << 1)) | ((uint64_t)t2 << 32);
+        } else {
+            ((uint32_t *)keys)[p] = (t0 | (t1 << 1)) | (t2 << 16);  // 8 fields: bits 0..15 and 16..30
+        }
+    } else if (key_kind == kTherm32) {
+        // 16-bit fingerprint, thermometer code of its popcount above it
+        ((uint32_t *)keys)[p] = fp | (((1u << __builtin_popcount(fp)) - 1u) << 16);
+    } else {
+        ((uint32_t *)keys)[p] = fp;
+    }
 }
 
 template <int VARIANT>
@@ -203,25 +240,57 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
         fp_sorted[p] = fp;
     if (fp_orig)
         fp_orig[perm[p]] = fp;
-    if (!keys)
+    if (keys)
+        store_key<VARIANT>(fp, key_kind, keys, p);
+}
+
+// k_layout followed by the fingerprint of each string, built from the
+// dwords as they are written (one pass over the bytes).
+template <int VARIANT>
+__global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit,
+                                                   const uint32_t *perm, const uint32_t *len, const uint32_t *off,
+                                                   const uint32_t *bdw, uint32_t n, uint8_t *slen, uint32_t *soff,
+                                                   uint32_t *str, uint64_t str_cap, uint32_t *err, const uint8_t *map,
+                                                   int bits, uint32_t *fp_orig, void *keys, int key_kind)
+{
+    __shared__ uint8_t smap[256];
+    smap[threadIdx.x] = map[threadIdx.x];
+    __syncthreads();
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
         return;
-    if (VARIANT == 1) {
-        // thermometer expansion of each 2-bit count v: [v>=1, v>=2, v>=3];
-        // the popcount of the XOR of two expansions is the L1 distance of
-        // the counts.
-        const uint32_t lo = fp & 0x55555555u, hi = (fp >> 1) & 0x55555555u;
-        const uint32_t t0 = lo | hi, t1 = hi, t2 = lo & hi;
-        if (key_is_64(key_kind)) {
-            ((uint64_t *)keys)[p] = (uint64_t)(t0 | (t1 << 1)) | ((uint64_t)t2 << 32);
-        } else {
-            ((uint32_t *)keys)[p] = (t0 | (t1 << 1)) | (t2 << 16);  // 8 fields: bits 0..15 and 16..30
-        }
-    } else if (key_kind == kTherm32) {
-        // 16-bit fingerprint, thermometer code of its popcount above it
-        ((uint32_t *)keys)[p] = fp | (((1u << __builtin_popcount(fp)) - 1u) << 16);
+    const uint32_t npos = (uint32_t)bits / 3;
+    uint32_t fp = fp_init<VARIANT>(npos);
+    const uint32_t i = perm[p];
+    const uint32_t L = len[i];
+    const uint32_t sw = slot_dwords(L);
+    const uint32_t so = bdw[L] + (p - off[L]) * sw;
+    if ((uint64_t)so + sw > str_cap) {
+        atomicOr(err, 4u);
+        slen[p] = 0;
+        soff[p] = 0;
     } else {
-        ((uint32_t *)keys)[p] = fp;
+        slen[p] = (uint8_t)L;
+        soff[p] = so;
+        const uint64_t start = offsets[i];
+        const uint64_t end_all = offsets[n];
+        const uint64_t limit = end_all < nbytes_limit ? end_all : nbytes_limit;
+        for (uint32_t t = 0; t < sw; ++t) {
+            uint32_t w = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t pos = 4 * t + j;
+                const uint64_t a = start + pos;
+                if (pos < L && a < limit)
+                    w |= (uint32_t)bytes[a] << (8 * j);
+            }
+            str[so + t] = w;
+            fp_dword<VARIANT>(fp, w, t, L, smap, npos);
+        }
     }
+    if (fp_orig)
+        fp_orig[i] = fp;
+    store_key<VARIANT>(fp, key_kind, keys, p);
 }
 
 // Reorder a laid-out set inside its length blocks by key popcount (stable):
@@ -364,6 +433,34 @@ void launch_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbyte
         return;
     hipLaunchKernelGGL(k_layout, dim3(blocks_for(n, 256)), dim3(256), 0, s, bytes, offsets, nbytes_limit, perm, len,
                        off, bdw, n, slen, soff, str, str_cap, err);
+}
+
+void launch_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit, const uint32_t *perm,
+                      const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
+                      uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err, const uint8_t *map, int variant,
+                      int bits, uint32_t *fp_orig, void *keys, int key_kind, hipStream_t s)
+{
+    if (n == 0)
+        return;
+    dim3 g(blocks_for(n, 256)), b(256);
+#define FPM_LAYOUT_FP(V)                                                                                              \
+    hipLaunchKernelGGL(k_layout_fp<V>, g, b, 0, s, bytes, offsets, nbytes_limit, perm, len, off, bdw, n, slen, soff,  \
+                       str, str_cap, err, map, bits, fp_orig, keys, key_kind)
+    switch (variant) {
+    case 0:
+        FPM_LAYOUT_FP(0);
+        break;
+    case 1:
+        FPM_LAYOUT_FP(1);
+        break;
+    case 2:
+        FPM_LAYOUT_FP(2);
+        break;
+    default:
+        FPM_LAYOUT_FP(3);
+        break;
+    }
+#undef FPM_LAYOUT_FP
 }
 
 void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_t *slen, const uint32_t *perm,

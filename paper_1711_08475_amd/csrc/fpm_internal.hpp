@@ -89,6 +89,13 @@ struct MatchCounters {
     uint64_t *verify_cells; // sum (2k+1) * min(m, n)
 };
 
+// Destination of the last pass of the match-list sort (out == nullptr: none).
+struct Unpack {
+    uint32_t *out = nullptr;
+    uint32_t wbits = 0;
+    int pairs_only = 0;
+};
+
 struct MatchArgs {
     StrSetView q, d;
     WorkList wl;
@@ -132,6 +139,13 @@ void launch_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbyte
                    const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
                    uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err, hipStream_t s);
 
+// launch_layout and the fingerprints (Section 3.2) of the strings in one
+// pass: fp_orig[perm[p]] (optional) and the filter keys (required).
+void launch_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit, const uint32_t *perm,
+                      const uint32_t *len, const uint32_t *off, const uint32_t *bdw, uint32_t n, uint8_t *slen,
+                      uint32_t *soff, uint32_t *str, uint64_t str_cap, uint32_t *err, const uint8_t *map, int variant,
+                      int bits, uint32_t *fp_orig, void *keys, int key_kind, hipStream_t s);
+
 // Fingerprints (Section 3.2) of the sorted padded strings: fp_sorted[p],
 // fp_orig[perm[p]] (optional) and the filter keys.
 void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_t *slen, const uint32_t *perm,
@@ -169,14 +183,13 @@ hipError_t launch_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
 void launch_invert(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t s);
 
 // ----------------------------------------------------------------- sort
-// Stable LSD radix sort of n64 keys (count read from device) on bits
-// [lo_bit, hi_bit), kSortBits per pass; ping-pongs between keys and tmp and
-// returns the buffer that holds the result (keys for an even pass count,
-// else tmp).  scratch: kRadixScratch uint32.
-const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
-                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s);
-// Packed keys -> fpm_match triples (count read from device, clamped to cap).
-void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,
-                   int pairs_only, hipStream_t s);
+// Stable LSD radix sort of packed match keys (count read from device,
+// clamped to cap) on bits [lo_bit, hi_bit), kSortBits per pass, ping-pong
+// between keys and tmp; the last pass writes each key straight to triples as
+// (query, word, dist) (pairs_only: (query, word)), word = the wbits above
+// the 2 dist bits.  scratch: kRadixScratch uint32.
+void launch_sort_unpack(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
+                        uint32_t hi_bit, uint32_t wbits, uint32_t *triples, int pairs_only, uint32_t *scratch,
+                        hipStream_t s);
 
 }  // namespace fpm

@@ -122,7 +122,27 @@ __device__ __forceinline__ void digit_bases(const uint32_t *totals, uint32_t *ba
     __syncthreads();
 }
 
+// Packed match key (query | word | dist, dist in the low 2 bits, the word
+// in the next wbits) -> (query, word, dist) triple, or (query, word) pair.
+__device__ __forceinline__ void unpack_key(uint64_t k, uint64_t pos, const Unpack &u)
+{
+    const uint64_t wmask = (u.wbits >= 64) ? ~0ull : ((1ull << u.wbits) - 1ull);
+    const uint32_t d = (uint32_t)(k & 3ull);
+    const uint32_t w = (uint32_t)((k >> 2) & wmask);
+    const uint32_t q = (uint32_t)(k >> (2 + u.wbits));
+    if (u.pairs_only) {
+        u.out[2 * pos] = q;
+        u.out[2 * pos + 1] = w;
+    } else {
+        u.out[3 * pos] = q;
+        u.out[3 * pos + 1] = w;
+        u.out[3 * pos + 2] = d;
+    }
+}
+
 // kScatterWaves waves per block.  vals_in == nullptr means value = item index.
+// With un.out set (last pass of the match-list sort) a key is written as its
+// unpacked triple at its sorted position instead.
 constexpr int kScatterWaves = 16;
 
 template <typename K, int BITS>
@@ -130,7 +150,7 @@ __global__ void __launch_bounds__(64 * kScatterWaves) k_radix_scatter(const K *k
                                                                       K *keys_out, uint32_t *vals_out,
                                                                       const uint64_t *dcount, uint64_t hcount,
                                                                       uint64_t cap, uint32_t shift,
-                                                                      const uint32_t *offs)
+                                                                      const uint32_t *offs, Unpack un)
 {
     constexpr uint32_t BINS = 1u << BITS, MASK = BINS - 1u;
     static_assert(BINS <= 64 * kScatterWaves, "one thread per digit in the prefix step");
@@ -183,7 +203,9 @@ __global__ void __launch_bounds__(64 * kScatterWaves) k_radix_scatter(const K *k
         if (active) {
             const uint32_t rank = (uint32_t)__popcll(peers & below);
             const uint32_t pos = start + rank;
-            if (keys_out)
+            if (un.out)
+                unpack_key((uint64_t)key, pos, un);
+            else if (keys_out)
                 keys_out[pos] = key;
             if (vals_out)
                 vals_out[pos] = val;
@@ -222,37 +244,16 @@ __global__ void __launch_bounds__(256) k_bucket_tables(const uint32_t *offs, uin
         bdw[256] = part[255];
 }
 
-__global__ void k_unpack(const uint64_t *keys, const uint64_t *dcount, uint64_t cap, uint32_t wbits,
-                         uint32_t *triples, int pairs_only)
-{
-    const uint64_t n = range_n(dcount, 0, cap);
-    const uint64_t wmask = (wbits >= 64) ? ~0ull : ((1ull << wbits) - 1ull);
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = keys[i];
-        const uint32_t d = (uint32_t)(k & 3ull);
-        const uint32_t w = (uint32_t)((k >> 2) & wmask);
-        const uint32_t q = (uint32_t)(k >> (2 + wbits));
-        if (pairs_only) {
-            triples[2 * i] = q;
-            triples[2 * i + 1] = w;
-        } else {
-            triples[3 * i] = q;
-            triples[3 * i + 1] = w;
-            triples[3 * i + 2] = d;
-        }
-    }
-}
-
 template <typename K, int BITS>
 void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout, const uint64_t *dcount, uint64_t hcount,
-                uint64_t cap, uint32_t shift, uint32_t *scratch, hipStream_t s)
+                uint64_t cap, uint32_t shift, uint32_t *scratch, hipStream_t s, Unpack un = Unpack{})
 {
     hipLaunchKernelGGL((k_radix_hist<K, BITS>), dim3(kRadixBlocks), dim3(256), 0, s, kin, dcount, hcount, cap, shift,
                        scratch);
     hipLaunchKernelGGL(k_scan_rows, dim3((1 << BITS) / 16), dim3(1024), 0, s, scratch,
                        scratch + ((size_t)(1 << BITS) << kRadixShift));
     hipLaunchKernelGGL((k_radix_scatter<K, BITS>), dim3(kRadixBlocks), dim3(64 * kScatterWaves), 0, s, kin, vin, kout, vout,
-                       dcount, hcount, cap, shift, scratch);
+                       dcount, hcount, cap, shift, scratch, un);
 }
 
 }  // namespace
@@ -264,23 +265,19 @@ void launch_length_sort(const uint32_t *len, uint32_t n, uint32_t *perm, uint32_
     hipLaunchKernelGGL(k_bucket_tables, dim3(1), dim3(256), 0, s, scratch, n, off, bdw);
 }
 
-const uint64_t *launch_sort_keys(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap,
-                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t *scratch, hipStream_t s)
+void launch_sort_unpack(uint64_t *keys, uint64_t *tmp, const uint64_t *count, uint64_t cap, uint32_t lo_bit,
+                        uint32_t hi_bit, uint32_t wbits, uint32_t *triples, int pairs_only, uint32_t *scratch,
+                        hipStream_t s)
 {
     uint64_t *a = keys, *b = tmp;
     for (uint32_t shift = lo_bit; shift < hi_bit; shift += kSortBits) {
-        radix_pass<uint64_t, kSortBits>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s);
+        const bool last = shift + kSortBits >= hi_bit;
+        radix_pass<uint64_t, kSortBits>(a, nullptr, b, nullptr, count, 0, cap, shift, scratch, s,
+                                        last ? Unpack{triples, wbits, pairs_only} : Unpack{});
         uint64_t *t = a;
         a = b;
         b = t;
     }
-    return a;
-}
-
-void launch_unpack(const uint64_t *keys, const uint64_t *count, uint64_t cap, uint32_t wbits, uint32_t *triples,
-                   int pairs_only, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_unpack, dim3(1024), dim3(256), 0, s, keys, count, cap, wbits, triples, pairs_only);
 }
 
 }  // namespace fpm

@@ -245,11 +245,13 @@ void fpm_plan_destroy(fpm_plan *plan);
 /* Autotuner for the batched schedule: times every combination of
  * queries_per_item in {16, 32, 64, 128, 256}, slab in {512, 1024, 2048,
  * 4096, 8192, 16384} and both bucket orders on the given device queries with
- * the tail split of *best (on entry), then the fastest of those with tail
- * splits 10, 25 and 40 (100 = none), and writes the fastest overall into *best
- * (its schedule = FPM_SCHED_BATCHED).  `timings_out` (nullable) receives up
- * to `max_timings` rows of (queries_per_item, slab, bucket_order,
- * tail_split, ms) as floats. */
+ * the tail split and filter rule (bound) of *best (on entry), then the
+ * fastest of those with tail splits 10, 25 and 40 (100 = none), then times the
+ * four fastest configurations again with max(8, 4 * repeats) runs each and
+ * writes the fastest of those into *best (its schedule = FPM_SCHED_BATCHED).
+ * `timings_out` (nullable) receives up to `max_timings` rows of
+ * (queries_per_item, slab, bucket_order, tail_split, ms) as floats, the
+ * longer re-timings last. */
 fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint64_t *d_qoffsets, uint32_t n_queries,
                         uint64_t query_bytes, fpm_metric metric, uint32_t k, uint32_t repeats, fpm_options *best,
                         float *timings_out, uint32_t max_timings, uint32_t *n_timings);

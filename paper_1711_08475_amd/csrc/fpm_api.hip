@@ -1122,8 +1122,9 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
         base.tail_split = 100;
     float best_ms = 1e30f;
     uint32_t nt = 0;
+    std::vector<std::pair<float, fpm_options>> seen;
     // time one configuration; the fastest so far goes to *best
-    auto trial = [&](fpm_options o) -> fpm_status {
+    auto trial = [&](fpm_options o, uint32_t repeats) -> fpm_status {
         o.schedule = FPM_SCHED_BATCHED;
         if (!o.use_graph)
             o.use_graph = 1;
@@ -1146,6 +1147,7 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
         if (st)
             return st;
         const float ms = tot / repeats;
+        seen.emplace_back(ms, o);
         if (timings_out && nt < max_timings) {
             timings_out[5 * nt + 0] = (float)o.queries_per_item;
             timings_out[5 * nt + 1] = (float)o.slab;
@@ -1167,7 +1169,7 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
                 o.queries_per_item = qt;
                 o.slab = sl;
                 o.bucket_order = order;
-                if (fpm_status st = trial(o))
+                if (fpm_status st = trial(o, repeats))
                     return st;
             }
         }
@@ -1178,9 +1180,18 @@ fpm_status fpm_autotune(const fpm_index *ix, const uint8_t *d_qbytes, const uint
             continue;
         fpm_options o = grid_best;
         o.tail_split = tl;
-        if (fpm_status st = trial(o))
+        if (fpm_status st = trial(o, repeats))
             return st;
     }
+    // the short timings above are a few percent noisy: time the four fastest
+    // again, longer, and keep the fastest of those
+    std::vector<std::pair<float, fpm_options>> top(seen);
+    std::sort(top.begin(), top.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    top.resize(std::min<size_t>(top.size(), 4));
+    best_ms = 1e30f;
+    for (const auto &c : top)
+        if (fpm_status st = trial(c.second, std::max<uint32_t>(8, 4 * repeats)))
+            return st;
     if (n_timings)
         *n_timings = std::min(nt, max_timings);
     return FPM_OK;

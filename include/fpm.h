@@ -41,7 +41,7 @@
  * pointer, decreasing offsets, a string longer than 255, bits not 16 or 32, a
  * custom map entry >= the variant's field count, a bad option.
  * FPM_EUNSUPPORTED: position or occurrence-halved fingerprints with the
- * Levenshtein metric (Section 3 restricts both to Hamming), k outside 1..2
+ * Levenshtein metric (Section 3 restricts both to Hamming), k outside 1..3
  * for matching.  FPM_ENOMEM / FPM_EDEVICE: a HIP allocation or launch failed.
  *
  * Threads: an index is immutable after it is built and may be shared by

@@ -522,8 +522,8 @@ static fpm_status check_metric(const fpm_index *ix, fpm_metric metric, uint32_t 
 {
     if (metric != FPM_HAM && metric != FPM_LEV)
         return fail(FPM_EINVAL, "unknown metric %d", (int)metric);
-    if (k < 1 || k > 2)
-        return fail(FPM_EUNSUPPORTED, "k = %u: the GPU matcher supports k = 1 and k = 2", k);
+    if (k < 1 || k > (uint32_t)kMaxK)
+        return fail(FPM_EUNSUPPORTED, "k = %u: the GPU matcher supports k = 1 .. %d", k, kMaxK);
     if (metric == FPM_LEV && (ix->variant == FPM_POS || ix->variant == FPM_OCCH))
         return fail(FPM_EUNSUPPORTED, "position and occurrence-halved fingerprints are sound for Hamming only");
     return FPM_OK;
@@ -1073,8 +1073,8 @@ fpm_status fpm_verify_pairs(const fpm_index *ix, const uint8_t *qbytes, const ui
         return fail(FPM_EINVAL, "null pointer");
     if (metric != FPM_HAM && metric != FPM_LEV)
         return fail(FPM_EINVAL, "unknown metric");
-    if (k < 1 || k > 2)
-        return fail(FPM_EUNSUPPORTED, "k must be 1 or 2");
+    if (k < 1 || k > (uint32_t)kMaxK)
+        return fail(FPM_EUNSUPPORTED, "k must be 1 .. %d", kMaxK);
     fpm_status st = check_csr(qbytes, qoffsets, n_queries, "queries");
     if (st || n_pairs == 0)
         return st;

@@ -22,7 +22,8 @@ namespace fpm {
 
 constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
-constexpr int kMaxPairs = 2 * 256 * 5;  // (query length, word length) pairs, |dL| <= 2, full + tail part
+constexpr int kMaxK = 3;                // largest supported k (match keys hold the distance in 2 bits)
+constexpr int kMaxPairs = 2 * 256 * (2 * kMaxK + 1);  // (query length, word length) pairs, |dL| <= k, full + tail part
 constexpr int kRadixShift = 7;
 constexpr int kRadixBlocks = 1 << kRadixShift;  // blocks of one stable radix pass (16 waves each)
 constexpr int kSortBits = 9;                    // digit width of the match-list sort (lengths use 8)

@@ -960,11 +960,15 @@ hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persiste
     if (metric == 0) {
         if (k == 1)
             return launch_kmk<KIND, 0, 1>(a, persistent, pblocks, host_items, s);
-        return launch_kmk<KIND, 0, 2>(a, persistent, pblocks, host_items, s);
+        if (k == 2)
+            return launch_kmk<KIND, 0, 2>(a, persistent, pblocks, host_items, s);
+        return launch_kmk<KIND, 0, 3>(a, persistent, pblocks, host_items, s);
     }
     if (k == 1)
         return launch_kmk<KIND, 1, 1>(a, persistent, pblocks, host_items, s);
-    return launch_kmk<KIND, 1, 2>(a, persistent, pblocks, host_items, s);
+    if (k == 2)
+        return launch_kmk<KIND, 1, 2>(a, persistent, pblocks, host_items, s);
+    return launch_kmk<KIND, 1, 3>(a, persistent, pblocks, host_items, s);
 }
 
 }  // namespace
@@ -1014,13 +1018,15 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k
     case kPos16:
         if (metric != 0)
             return hipErrorInvalidValue;
-        return k == 1 ? launch_kmk<kPos16, 0, 1>(a, persistent, persistent_blocks, host_items, s)
-                      : launch_kmk<kPos16, 0, 2>(a, persistent, persistent_blocks, host_items, s);
+        return k == 1   ? launch_kmk<kPos16, 0, 1>(a, persistent, persistent_blocks, host_items, s)
+               : k == 2 ? launch_kmk<kPos16, 0, 2>(a, persistent, persistent_blocks, host_items, s)
+                        : launch_kmk<kPos16, 0, 3>(a, persistent, persistent_blocks, host_items, s);
     case kPos32:
         if (metric != 0)
             return hipErrorInvalidValue;
-        return k == 1 ? launch_kmk<kPos32, 0, 1>(a, persistent, persistent_blocks, host_items, s)
-                      : launch_kmk<kPos32, 0, 2>(a, persistent, persistent_blocks, host_items, s);
+        return k == 1   ? launch_kmk<kPos32, 0, 1>(a, persistent, persistent_blocks, host_items, s)
+               : k == 2 ? launch_kmk<kPos32, 0, 2>(a, persistent, persistent_blocks, host_items, s)
+                        : launch_kmk<kPos32, 0, 3>(a, persistent, persistent_blocks, host_items, s);
     case kTherm32:
         return launch_kind<kTherm32>(a, metric, k, persistent, persistent_blocks, host_items, s);
     case kAsym32:
@@ -1039,17 +1045,23 @@ hipError_t launch_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
     if (n == 0)
         return hipSuccess;
     const dim3 g((uint32_t)((n + 255) / 256)), b(256);
+#define FPM_VERIFY_PAIRS(M, K) hipLaunchKernelGGL((k_verify_pairs<M, K>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist)
     if (metric == 0) {
         if (k == 1)
-            hipLaunchKernelGGL((k_verify_pairs<0, 1>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+            FPM_VERIFY_PAIRS(0, 1);
+        else if (k == 2)
+            FPM_VERIFY_PAIRS(0, 2);
         else
-            hipLaunchKernelGGL((k_verify_pairs<0, 2>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+            FPM_VERIFY_PAIRS(0, 3);
     } else {
         if (k == 1)
-            hipLaunchKernelGGL((k_verify_pairs<1, 1>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+            FPM_VERIFY_PAIRS(1, 1);
+        else if (k == 2)
+            FPM_VERIFY_PAIRS(1, 2);
         else
-            hipLaunchKernelGGL((k_verify_pairs<1, 2>), g, b, 0, s, q, qinv, d, dinv, pairs, n, dist);
+            FPM_VERIFY_PAIRS(1, 3);
     }
+#undef FPM_VERIFY_PAIRS
     return hipGetLastError();
 }
 

@@ -50,6 +50,8 @@ ASYM_CASES = [
     (oracle.COUNT, 16, oracle.HAM, 1), (oracle.OCCH, 32, oracle.HAM, 2),
     # 64-bit keys
     (oracle.COUNT, 32, oracle.LEV, 1), (oracle.COUNT, 32, oracle.LEV, 2),
+    # k = 3
+    (oracle.OCC, 16, oracle.LEV, 3), (oracle.OCC, 32, oracle.LEV, 3), (oracle.COUNT, 32, oracle.HAM, 3),
 ]
 
 
@@ -68,7 +70,7 @@ def test_asym_match_equals_oracle(fpm, small, variant, bits, metric, k, schedule
     assert st["pairs_examined"] == ex == ex_fd
     assert st["survivors"] == surv
     assert surv <= surv_fd
-    # the paper's rule on the same (popcount-ordered) index is unchanged
+    # the paper's rule on the same index is unchanged
     _, st_fd = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule), with_stats=True)
     assert st_fd["survivors"] == surv_fd
 

@@ -86,6 +86,9 @@ CASES = [
     (oracle.COUNT, 32, oracle.LEV, 2),
     (oracle.POS, 16, oracle.HAM, 1), (oracle.POS, 32, oracle.HAM, 1), (oracle.POS, 16, oracle.HAM, 2),
     (oracle.OCCH, 16, oracle.HAM, 1), (oracle.OCCH, 32, oracle.HAM, 2),
+    # k = 3 (larger k, Section 5)
+    (oracle.OCC, 16, oracle.LEV, 3), (oracle.OCC, 32, oracle.HAM, 3), (oracle.COUNT, 32, oracle.LEV, 3),
+    (oracle.POS, 16, oracle.HAM, 3), (oracle.OCCH, 32, oracle.HAM, 3),
 ]
 
 
@@ -107,7 +110,8 @@ def test_match_equals_oracle(fpm, small, variant, bits, metric, k, schedule):
     assert st["pairs_logical"] == (d[1].size - 1) * (q[1].size - 1)
 
 
-@pytest.mark.parametrize("metric,k", [(oracle.HAM, 1), (oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 2)])
+@pytest.mark.parametrize("metric,k", [(oracle.HAM, 1), (oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 2),
+                                      (oracle.LEV, 3), (oracle.HAM, 3)])
 def test_bruteforce_equals_oracle(fpm, small, metric, k):
     d, q = small
     say("brute force", metric, k)
@@ -148,7 +152,9 @@ def test_verify_pairs(fpm, small):
     ref_pairs = oracle_match("small", d, q, oracle.LEV, 2)[:, :2]
     pairs = np.concatenate([pairs, ref_pairs])
     ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
-    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1), (oracle.HAM, 2)]:
+    pairs = np.concatenate([pairs, oracle_match("small", d, q, oracle.LEV, 3)[:, :2]])
+    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1), (oracle.HAM, 2), (oracle.LEV, 3),
+                      (oracle.HAM, 3)]:
         say("verify pairs", metric, k)
         got = fpm.fpm_verify_pairs(ix, q, pairs, metric, k)
         ref = oracle.pair_dist(d, q, pairs, metric)
@@ -190,7 +196,7 @@ def test_everything_survives_and_ragged_buckets(fpm):
     queries = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(77)]
     d, q = datagen.to_csr(words), datagen.to_csr(queries)
     none = np.full(256, 255, dtype=np.uint8)
-    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
+    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1), (oracle.LEV, 3)]:
         ref = oracle.match(d, q, metric, k)
         for sched, qt, slab, tail in [(0, 16, 64, 0), (1, 32, 128, 0), (1, 1024, 1 << 20, 0), (0, 64, 16384, 0),
                                       (1, 16, 64, 99), (1, 64, 256, 50), (1, 32, 128, 100)]:
@@ -219,7 +225,7 @@ def test_errors(fpm, small):
     assert e.value.status == fpm.FPM_EUNSUPPORTED
     ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
     with pytest.raises(fpm.FpmError) as e:
-        fpm.fpm_match(ix, q, "lev", 3)
+        fpm.fpm_match(ix, q, "lev", 4)
     assert e.value.status == fpm.FPM_EUNSUPPORTED
     with pytest.raises(fpm.FpmError) as e:
         fpm.fpm_build_fingerprints(d, "occ", 8, "common")
@@ -315,6 +321,7 @@ def mixed_small():
 
 
 URL_CASES = [
+    (oracle.OCC, 32, oracle.LEV, 3), (oracle.COUNT, 32, oracle.HAM, 3),
     (oracle.OCC, 32, oracle.LEV, 1), (oracle.OCC, 32, oracle.LEV, 2), (oracle.COUNT, 32, oracle.LEV, 1),
     (oracle.COUNT, 32, oracle.LEV, 2), (oracle.OCC, 16, oracle.LEV, 2), (oracle.POS, 32, oracle.HAM, 2),
     (oracle.COUNT, 32, oracle.HAM, 1), (oracle.OCCH, 32, oracle.HAM, 1),

@@ -131,9 +131,9 @@ def _maps(rng, variant, bits, n=3):
 ])
 def test_asym_never_rejects_a_true_match_exhaustive(metric, variant):
     """Over all strings on {e,t,a,z} up to length 5, every pair within
-    distance d <= 2 has max(excess(q, w), excess(w, q)) <= d."""
+    distance d <= 3 has max(excess(q, w), excess(w, q)) <= d."""
     U = _tiny_universe("etaz", 5)
-    res = oracle.match(U, U, metric, 2)
+    res = oracle.match(U, U, metric, 3)
     rng = np.random.default_rng(11)
     for bits in (16, 32):
         for mp in _maps(rng, variant, bits):

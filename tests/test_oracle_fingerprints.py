@@ -243,9 +243,9 @@ def _tiny_universe(alphabet: str, max_len: int):
 ])
 def test_eq1_never_rejects_a_true_match_exhaustive(metric, variant):
     """Eq. 1: D >= ceil(F_D/2).  Over all strings on {e,t,a,z} up to length 5
-    and several symbol maps, every pair within k <= 2 keeps F_D <= 2k."""
+    and several symbol maps, every pair within k <= 3 keeps F_D <= 2k."""
     U = _tiny_universe("etaz", 5)
-    res = oracle.match(U, U, metric, 2)
+    res = oracle.match(U, U, metric, 3)
     rng = np.random.default_rng(3)
     for bits in (16, 32):
         for mp in random_maps(rng, variant, bits, n=3):

@@ -15,7 +15,8 @@ function computes, and the passage of the paper it follows:
   (query, word) (the dictionary-matching problem of Section 1).
 * ``select_symbols``: common / rare / mixed symbol sets (Section 3).
 * ``fingerprints``: occurrence, occurrence-halved, count, position
-  constructions (Section 3.2).
+  constructions (Section 3.2), and hashed bigram occurrence (``QGRAM``, the
+  q-gram direction of the future work in Section 5).
 * ``fd``: fingerprint distance F_D (Section 3.3); a pair is rejected when
   ceil(F_D/2) > k (Eq. 1), i.e. survives when F_D <= 2k.
 * ``filter_stats``: examined / surviving pair counts under Eq. 1.
@@ -32,7 +33,7 @@ import os
 import numpy as np
 
 HAM, LEV = 0, 1
-OCC, COUNT, POS, OCCH = 0, 1, 2, 3
+OCC, COUNT, POS, OCCH, QGRAM = 0, 1, 2, 3, 4
 COMMON, RARE, MIXED = 0, 1, 2
 NONE = 0xFF
 INF = 0xFFFFFFFF
@@ -87,6 +88,8 @@ def _load():
     lib.orc_filter_stats.restype = ctypes.c_int
     lib.orc_filter_stats.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, ctypes.c_int,
                                      ctypes.c_uint32, u8p, ctypes.c_int, ctypes.c_uint32, u64p]
+    lib.orc_threshold.restype = ctypes.c_uint32
+    lib.orc_threshold.argtypes = [ctypes.c_int, ctypes.c_uint32]
     lib.orc_excess.restype = ctypes.c_uint32
     lib.orc_excess.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32]
     lib.orc_excess_many.restype = None
@@ -228,6 +231,11 @@ def fd(a, b, variant: int, bits: int, literal: bool = False):
     _load().orc_fd_many(_ptr(x, ctypes.c_uint32), _ptr(y, ctypes.c_uint32), x.size, variant, bits,
                         1 if literal else 0, _ptr(out, ctypes.c_uint32))
     return out
+
+
+def threshold(variant: int, k: int) -> int:
+    """Largest F_D of a pair within distance k: 2k (Eq. 1), 4k for bigrams."""
+    return int(_load().orc_threshold(variant, k))
 
 
 def excess(a, b, variant: int, bits: int):

@@ -49,6 +49,7 @@
 #define ORC_COUNT 1
 #define ORC_POS 2
 #define ORC_OCCH 3
+#define ORC_QGRAM 4  /* hashed bigram occurrence (q = 2); future work of Section 5 */
 
 #define ORC_COMMON 0
 #define ORC_RARE 1
@@ -333,6 +334,8 @@ int orc_num_fields(int variant, uint32_t bits)
         return (int)bits / 2;
     case ORC_POS:
         return (int)(bits / 3) + (int)(bits % 3);
+    case ORC_QGRAM:
+        return (int)bits; /* fields are hash buckets; the symbol map is not used */
     default:
         return -1;
     }
@@ -521,6 +524,26 @@ static uint32_t fp_pos(const uint8_t *s, uint32_t n, const uint8_t *map, uint32_
     return fp;
 }
 
+/* q-gram occurrence (q = 2), an extension in the direction the paper names
+ * as future work (Section 5): every bigram (s[i], s[i+1]) of the raw bytes
+ * goes to one of the `bits` fields by Knuth's multiplicative hash of the
+ * 16-bit value v = s[i] * 256 + s[i+1]: field = (v * 2654435761 mod 2^32)
+ * >> (32 - log2(bits)); the field's bit is set.  Strings shorter than 2
+ * have no bigram (fingerprint 0). */
+static uint32_t fp_qgram(const uint8_t *s, uint32_t n, uint32_t bits)
+{
+    uint32_t lg = 0;
+    while ((1u << lg) < bits)
+        lg++;
+    uint32_t fp = 0;
+    for (uint32_t i = 0; i + 1 < n; ++i) {
+        uint32_t v = (uint32_t)s[i] * 256u + (uint32_t)s[i + 1];
+        uint32_t h = (uint32_t)((uint64_t)v * 2654435761ull % 4294967296ull);
+        fp |= 1u << (h >> (32 - lg));
+    }
+    return fp;
+}
+
 /* Fingerprint of one string.  Map entries must be < orc_num_fields or
  * ORC_NONE (checked by orc_check_map). */
 uint32_t orc_fp(const uint8_t *s, uint32_t n, int variant, uint32_t bits, const uint8_t *map)
@@ -534,6 +557,8 @@ uint32_t orc_fp(const uint8_t *s, uint32_t n, int variant, uint32_t bits, const 
         return fp_count(s, n, map);
     case ORC_POS:
         return fp_pos(s, n, map, bits);
+    case ORC_QGRAM:
+        return fp_qgram(s, n, bits);
     default:
         return 0;
     }
@@ -576,7 +601,7 @@ static uint32_t popcount32(uint32_t x)
 }
 
 /* F_D of two fingerprints.
- *   occ, occ-halved: Hamming weight of the XOR;
+ *   occ, occ-halved, q-gram: Hamming weight of the XOR;
  *   count: L1 distance of the 2-bit saturated counts (sound reading);
  *          with literal != 0: the Hamming weight of the XOR as printed;
  *   pos:   number of position fields that differ + Hamming weight of the XOR
@@ -586,6 +611,7 @@ uint32_t orc_fd(uint32_t a, uint32_t b, int variant, uint32_t bits, int literal)
     switch (variant) {
     case ORC_OCC:
     case ORC_OCCH:
+    case ORC_QGRAM:
         return popcount32(a ^ b);
     case ORC_COUNT: {
         if (literal)
@@ -648,6 +674,12 @@ void orc_excess_many(const uint32_t *a, const uint32_t *b, uint64_t n, int varia
         out[i] = orc_excess(a[i], b[i], variant, bits);
 }
 
+/* Largest F_D a pair within distance k can have: 2k (Eq. 1: one edit moves
+ * F_D by at most 2, Theorems 1 and 2); for bigram fingerprints 4k (one edit
+ * removes at most two bigram occurrences and adds at most two, so F_D moves
+ * by at most 4). */
+uint32_t orc_threshold(int variant, uint32_t k) { return variant == ORC_QGRAM ? 4 * k : 2 * k; }
+
 /* Filter statistics over all (query, word) pairs.  A pair is examined when
  * it can match at all by length (Ham: equal lengths; Lev: |m-n| <= k); it
  * survives when ceil(F_D/2) <= k, i.e. F_D <= 2k (Eq. 1).  counts[0] =
@@ -675,9 +707,9 @@ int orc_filter_stats(const uint8_t *dbytes, const uint64_t *doffs, uint32_t nd,
             if (!examined)
                 continue;
             counts[0]++;
-            if (orc_fd(qfp, dfp[w], variant, bits, 0) <= 2 * k)
+            if (orc_fd(qfp, dfp[w], variant, bits, 0) <= orc_threshold(variant, k))
                 counts[1]++;
-            if (orc_fd(qfp, dfp[w], variant, bits, 1) <= 2 * k)
+            if (orc_fd(qfp, dfp[w], variant, bits, 1) <= orc_threshold(variant, k))
                 counts[2]++;
         }
     }

@@ -13,7 +13,7 @@
  *   symbol, saturating) or position (p = 3 bits per symbol, first position,
  *   all ones when >= 2^p - 1 or absent, leftover bits are occurrence bits).
  *   Comparison (Section 3.3, Eq. 1): D(S1, S2) >= ceil(F_D / 2), so a pair is
- *   rejected without verification when F_D > 2k.  Survivors are verified
+ *   rejected without verification when F_D > 2k (bigram fingerprints: 4k).  Survivors are verified
  *   exactly (Ham: mismatches up to k + 1; Lev: the 2k+1 band).
  *
  * Readings fixed by this library where the paper is silent or inconsistent:
@@ -65,7 +65,13 @@ typedef enum {
     FPM_EDEVICE = -4
 } fpm_status;
 
-typedef enum { FPM_OCC = 0, FPM_COUNT = 1, FPM_POS = 2, FPM_OCCH = 3 } fpm_variant;
+/* FPM_QGRAM: bigram (q = 2) fingerprints, the q-gram direction of the
+ * paper's future work (Section 5).  Every bigram (x, y) of the raw bytes sets
+ * bit ((x * 256 + y) * 2654435761 mod 2^32) >> (32 - log2(bits)) (Knuth's
+ * multiplicative hash); the symbol map is not used (fpm_num_fields = bits).
+ * One edit replaces at most two bigrams, so F_D moves by at most 4 per edit
+ * and a pair is rejected when F_D > 4k (Ham and Lev). */
+typedef enum { FPM_OCC = 0, FPM_COUNT = 1, FPM_POS = 2, FPM_OCCH = 3, FPM_QGRAM = 4 } fpm_variant;
 typedef enum { FPM_HAM = 0, FPM_LEV = 1 } fpm_metric;
 typedef enum { FPM_COMMON = 0, FPM_RARE = 1, FPM_MIXED = 2, FPM_CUSTOM = 3 } fpm_symbols;
 
@@ -145,7 +151,8 @@ void fpm_free(void *p);
 
 /* Number of symbol fields of a fingerprint (Section 3 variants with the
  * Section 4 parameters b = 2, p = 3): occ bits, occh bits/2, count bits/2,
- * pos bits/3 + bits%3.  Returns -1 for an unknown variant or bits. */
+ * pos bits/3 + bits%3, qgram bits (hash buckets).  Returns -1 for an unknown
+ * variant or bits. */
 int fpm_num_fields(fpm_variant variant, uint32_t bits);
 
 /* Symbol selection (Section 3: common / rare / mixed sets).  A byte

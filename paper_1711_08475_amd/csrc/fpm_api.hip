@@ -57,6 +57,8 @@ uint32_t bits_for(uint64_t n)  // bits to index 0..n-1 (at least 1)
 
 int key_kind_for(int variant, uint32_t bits)
 {
+    if (variant == FPM_QGRAM)
+        return kQgram32;
     if (variant == FPM_COUNT && bits == 32)
         return kPop64;
     if (variant == FPM_POS)
@@ -67,7 +69,7 @@ int key_kind_for(int variant, uint32_t bits)
 // Keys for the asymmetric bound; -1 where it is not defined (position).
 int key_kind_asym(int variant, uint32_t bits)
 {
-    if (variant == FPM_POS)
+    if (variant == FPM_POS || variant == FPM_QGRAM)
         return -1;
     if (variant == FPM_COUNT)
         return bits == 32 ? kAsym64 : kAsym32;
@@ -297,6 +299,8 @@ int fpm_num_fields(fpm_variant variant, uint32_t bits)
         return (int)bits / 2;
     case FPM_POS:
         return (int)(bits / 3 + bits % 3);
+    case FPM_QGRAM:
+        return (int)bits;  // hash buckets; the symbol map is not used
     default:
         return -1;
     }
@@ -625,7 +629,8 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     p->asym = p->opt.bound == FPM_BOUND_ASYM && p->opt.schedule != FPM_SCHED_BRUTE;
     if (p->asym && ix->kind_asym < 0) {
         delete p;
-        return fail(FPM_EUNSUPPORTED, "the asymmetric bound is not defined for position fingerprints");
+        return fail(FPM_EUNSUPPORTED, "the asymmetric bound is offered for occurrence, occurrence-halved and count "
+                                      "fingerprints only");
     }
     p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : p->asym ? ix->kind_asym : ix->kind;
     hipError_t e = hipSuccess;

@@ -148,6 +148,10 @@ __global__ void k_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t
 //   pos  -> f < npos: first position (0-indexed) in 3 bits at 3f, all ones
 //           when it is >= 7 or the symbol is absent; f >= npos: occurrence
 //           bit 3*npos + (f - npos).
+// Bigram fingerprints (VARIANT 4, the q-gram direction of Section 5) ignore
+// the map: bigram (x, y) of the raw bytes sets bit
+// ((x * 256 + y) * 2654435761 mod 2^32) >> (32 - log2(bits)) (Knuth's
+// multiplicative hash); `aux` is log2(bits) for them and npos otherwise.
 template <int VARIANT>
 __device__ __forceinline__ uint32_t fp_init(uint32_t npos)
 {
@@ -157,10 +161,10 @@ __device__ __forceinline__ uint32_t fp_init(uint32_t npos)
 }
 
 // Symbols 4t .. 4t+3 of a string of length L (held in w, first symbol in the
-// low byte) into fp.
+// low byte) into fp; prev carries the last symbol of the previous dword.
 template <int VARIANT>
-__device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t w, uint32_t t, uint32_t L, const uint8_t *smap,
-                                         uint32_t npos)
+__device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t &prev, uint32_t w, uint32_t t, uint32_t L,
+                                         const uint8_t *smap, uint32_t npos)
 {
     const uint32_t half = L >> 1;
 #pragma unroll
@@ -168,6 +172,13 @@ __device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t w, uint32_t t, u
         const uint32_t pos = 4 * t + j;
         if (pos >= L)
             break;
+        if (VARIANT == 4) {
+            const uint32_t c = (w >> (8 * j)) & 0xFFu;
+            if (pos > 0)
+                fp |= 1u << (((prev * 256u + c) * 2654435761u) >> (32u - npos));
+            prev = c;
+            continue;
+        }
         const uint32_t f = smap[(w >> (8 * j)) & 0xFFu];
         if (f == 0xFFu)
             continue;
@@ -190,12 +201,18 @@ __device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t w, uint32_t t, u
 }
 
 template <int VARIANT>
+__device__ __forceinline__ uint32_t fp_aux(int bits)
+{
+    return VARIANT == 4 ? (bits == 16 ? 4u : 5u) : (uint32_t)bits / 3;
+}
+
+template <int VARIANT>
 __device__ __forceinline__ uint32_t fingerprint(const uint32_t *s, uint32_t L, const uint8_t *smap, uint32_t npos)
 {
-    uint32_t fp = fp_init<VARIANT>(npos);
+    uint32_t fp = fp_init<VARIANT>(npos), prev = 0;
     const uint32_t nw = (L + 3) >> 2;
     for (uint32_t t = 0; t < nw; ++t)
-        fp_dword<VARIANT>(fp, s[t], t, L, smap, npos);
+        fp_dword<VARIANT>(fp, prev, s[t], t, L, smap, npos);
     return fp;
 }
 
@@ -234,8 +251,8 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n)
         return;
-    const uint32_t npos = (uint32_t)bits / 3;
-    const uint32_t fp = fingerprint<VARIANT>(str + soff[p], slen[p], smap, npos);
+    const uint32_t aux = fp_aux<VARIANT>(bits);
+    const uint32_t fp = fingerprint<VARIANT>(str + soff[p], slen[p], smap, aux);
     if (fp_sorted)
         fp_sorted[p] = fp;
     if (fp_orig)
@@ -259,8 +276,8 @@ __global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const u
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n)
         return;
-    const uint32_t npos = (uint32_t)bits / 3;
-    uint32_t fp = fp_init<VARIANT>(npos);
+    const uint32_t npos = fp_aux<VARIANT>(bits);
+    uint32_t fp = fp_init<VARIANT>(npos), prev = 0;
     const uint32_t i = perm[p];
     const uint32_t L = len[i];
     const uint32_t sw = slot_dwords(L);
@@ -285,7 +302,7 @@ __global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const u
                     w |= (uint32_t)bytes[a] << (8 * j);
             }
             str[so + t] = w;
-            fp_dword<VARIANT>(fp, w, t, L, smap, npos);
+            fp_dword<VARIANT>(fp, prev, w, t, L, smap, npos);
         }
     }
     if (fp_orig)
@@ -456,8 +473,11 @@ void launch_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nb
     case 2:
         FPM_LAYOUT_FP(2);
         break;
-    default:
+    case 3:
         FPM_LAYOUT_FP(3);
+        break;
+    default:
+        FPM_LAYOUT_FP(4);
         break;
     }
 #undef FPM_LAYOUT_FP
@@ -470,24 +490,27 @@ void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_
     if (n == 0)
         return;
     dim3 g(blocks_for(n, 256)), b(256);
+#define FPM_FINGERPRINTS(V)                                                                                           \
+    hipLaunchKernelGGL(k_fingerprints<V>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig, keys,  \
+                       key_kind)
     switch (variant) {
     case 0:
-        hipLaunchKernelGGL(k_fingerprints<0>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
-                           keys, key_kind);
+        FPM_FINGERPRINTS(0);
         break;
     case 1:
-        hipLaunchKernelGGL(k_fingerprints<1>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
-                           keys, key_kind);
+        FPM_FINGERPRINTS(1);
         break;
     case 2:
-        hipLaunchKernelGGL(k_fingerprints<2>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
-                           keys, key_kind);
+        FPM_FINGERPRINTS(2);
+        break;
+    case 3:
+        FPM_FINGERPRINTS(3);
         break;
     default:
-        hipLaunchKernelGGL(k_fingerprints<3>, g, b, 0, s, str, soff, slen, perm, n, map, bits, fp_sorted, fp_orig,
-                           keys, key_kind);
+        FPM_FINGERPRINTS(4);
         break;
     }
+#undef FPM_FINGERPRINTS
 }
 
 void launch_pop_order(const uint32_t *off, const uint32_t *bdw, const uint32_t *str, const uint32_t *perm,

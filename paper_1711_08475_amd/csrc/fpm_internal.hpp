@@ -47,7 +47,19 @@ __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 //            larger excess and the Pop32 test applies unchanged;
 //   Asym32 / Asym64: the Pop32 / Pop64 keys, tested as
 //            popc(~(q & w)) + max(pq, pw) against the key width + k + 1.
-enum KeyKind : int { kPop32 = 0, kPop64 = 1, kPos16 = 2, kPos32 = 3, kAll = 4, kTherm32 = 5, kAsym32 = 6, kAsym64 = 7 };
+// Qgram32: bigram fingerprints, F_D = popc(kq ^ kw) rejected above 4k (one
+// edit replaces at most two bigrams).
+enum KeyKind : int {
+    kPop32 = 0,
+    kPop64 = 1,
+    kPos16 = 2,
+    kPos32 = 3,
+    kAll = 4,
+    kTherm32 = 5,
+    kAsym32 = 6,
+    kAsym64 = 7,
+    kQgram32 = 8
+};
 
 __host__ __device__ inline bool key_is_64(int kind) { return kind == kPop64 || kind == kAsym64; }
 

@@ -118,6 +118,11 @@ template <>
 struct Filter<kTherm32> : Filter<kPop32> {
 };
 
+// Bigram fingerprints: the same XOR popcount, against 4k (filter_neg).
+template <>
+struct Filter<kQgram32> : Filter<kPop32> {
+};
+
 // Asymmetric bound on full-width keys: with c = popc(q & w) the larger
 // excess is max(pq, pw) - c, and it is <= k iff
 // popc(~(q & w)) + max(pq, pw) - (width + k + 1) < 0.  Each side's popcount
@@ -177,7 +182,10 @@ struct Filter<kAsym64> {
 template <int KIND, int K>
 __host__ __device__ constexpr uint32_t filter_neg()
 {
-    return KIND == kAsym32 ? 0u - (32u + K + 1u) : KIND == kAsym64 ? 0u - (64u + K + 1u) : 0u - (2u * K + 1u);
+    return KIND == kAsym32    ? 0u - (32u + K + 1u)
+           : KIND == kAsym64  ? 0u - (64u + K + 1u)
+           : KIND == kQgram32 ? 0u - (4u * K + 1u)
+                              : 0u - (2u * K + 1u);
 }
 
 // Families of the asymmetric bound: e(q, w) - e(w, q) = pq - pw, so a pair
@@ -1033,6 +1041,8 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k
         return launch_kind<kAsym32>(a, metric, k, persistent, persistent_blocks, host_items, s);
     case kAsym64:
         return launch_kind<kAsym64>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kQgram32:
+        return launch_kind<kQgram32>(a, metric, k, persistent, persistent_blocks, host_items, s);
     default:
         return launch_kind<kAll>(a, metric, k, persistent, persistent_blocks, host_items, s);
     }

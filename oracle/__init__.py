@@ -16,7 +16,8 @@ function computes, and the passage of the paper it follows:
 * ``select_symbols``: common / rare / mixed symbol sets (Section 3).
 * ``fingerprints``: occurrence, occurrence-halved, count, position
   constructions (Section 3.2), and hashed bigram occurrence (``QGRAM``, the
-  q-gram direction of the future work in Section 5).
+  q-gram direction of the future work in Section 5), and occurrence + count
+  combined in one word (``COMBO``, F_D = the larger part's).
 * ``fd``: fingerprint distance F_D (Section 3.3); a pair is rejected when
   ceil(F_D/2) > k (Eq. 1), i.e. survives when F_D <= 2k.
 * ``filter_stats``: examined / surviving pair counts under Eq. 1.
@@ -33,7 +34,7 @@ import os
 import numpy as np
 
 HAM, LEV = 0, 1
-OCC, COUNT, POS, OCCH, QGRAM = 0, 1, 2, 3, 4
+OCC, COUNT, POS, OCCH, QGRAM, COMBO = 0, 1, 2, 3, 4, 5
 COMMON, RARE, MIXED = 0, 1, 2
 NONE = 0xFF
 INF = 0xFFFFFFFF

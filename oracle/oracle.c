@@ -50,6 +50,7 @@
 #define ORC_POS 2
 #define ORC_OCCH 3
 #define ORC_QGRAM 4  /* hashed bigram occurrence (q = 2); future work of Section 5 */
+#define ORC_COMBO 5  /* occurrence and count in one word; future work of Section 5 */
 
 #define ORC_COMMON 0
 #define ORC_RARE 1
@@ -336,6 +337,8 @@ int orc_num_fields(int variant, uint32_t bits)
         return (int)(bits / 3) + (int)(bits % 3);
     case ORC_QGRAM:
         return (int)bits; /* fields are hash buckets; the symbol map is not used */
+    case ORC_COMBO:
+        return (int)bits / 2; /* occurrence fields; the first bits/4 also have counters */
     default:
         return -1;
     }
@@ -544,6 +547,19 @@ static uint32_t fp_qgram(const uint8_t *s, uint32_t n, uint32_t bits)
     return fp;
 }
 
+/* Combined occurrence + count (Section 5 names combining fingerprint types
+ * as future work): the low bits/2 bits are the occurrence fingerprint of
+ * fields 0 .. bits/2 - 1; above them, the count fingerprint (2-bit saturating
+ * counters) of fields 0 .. bits/4 - 1 -- the map's first, most frequent
+ * fields get both. */
+static uint32_t fp_combo(const uint8_t *s, uint32_t n, const uint8_t *map, uint32_t bits)
+{
+    uint8_t cmap[256];
+    for (int c = 0; c < 256; ++c)
+        cmap[c] = (map[c] != ORC_NONE && map[c] < bits / 4) ? map[c] : (uint8_t)ORC_NONE;
+    return fp_occ(s, n, map) | (fp_count(s, n, cmap) << (bits / 2));
+}
+
 /* Fingerprint of one string.  Map entries must be < orc_num_fields or
  * ORC_NONE (checked by orc_check_map). */
 uint32_t orc_fp(const uint8_t *s, uint32_t n, int variant, uint32_t bits, const uint8_t *map)
@@ -559,6 +575,8 @@ uint32_t orc_fp(const uint8_t *s, uint32_t n, int variant, uint32_t bits, const 
         return fp_pos(s, n, map, bits);
     case ORC_QGRAM:
         return fp_qgram(s, n, bits);
+    case ORC_COMBO:
+        return fp_combo(s, n, map, bits);
     default:
         return 0;
     }
@@ -602,6 +620,7 @@ static uint32_t popcount32(uint32_t x)
 
 /* F_D of two fingerprints.
  *   occ, occ-halved, q-gram: Hamming weight of the XOR;
+ *   combined: the larger of the occurrence part's and the count part's F_D;
  *   count: L1 distance of the 2-bit saturated counts (sound reading);
  *          with literal != 0: the Hamming weight of the XOR as printed;
  *   pos:   number of position fields that differ + Hamming weight of the XOR
@@ -622,6 +641,14 @@ uint32_t orc_fd(uint32_t a, uint32_t b, int variant, uint32_t bits, int literal)
             d += (uint32_t)(ca > cb ? ca - cb : cb - ca);
         }
         return d;
+    }
+    case ORC_COMBO: {
+        /* each part is a sound F_D of its own (Theorem 1), so their maximum
+         * is one too: a pair survives when both parts are <= 2k */
+        uint32_t half = bits / 2, mask = (1u << half) - 1u;
+        uint32_t occ = popcount32((a ^ b) & mask);
+        uint32_t cnt = orc_fd(a >> half, b >> half, ORC_COUNT, half, 0);
+        return occ > cnt ? occ : cnt;
     }
     case ORC_POS: {
         uint32_t d = 0;

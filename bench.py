@@ -59,7 +59,8 @@ def metric_name(metric: str, k: int) -> str:
 PEAK_INT_OPS = 256 * 64 * 2.4e9  # CUs x lanes x clock: one 32-bit VALU op per lane per clock
 # VALU instructions per examined pair in the filter loop (see fpm_match.hip)
 FILTER_OPS = {("occ", 16): 3, ("occ", 32): 3, ("occh", 16): 3, ("occh", 32): 3, ("count", 16): 3, ("count", 32): 5,
-              ("pos", 16): 8, ("pos", 32): 8, ("qgram", 16): 3, ("qgram", 32): 3}
+              ("pos", 16): 8, ("pos", 32): 8, ("qgram", 16): 3, ("qgram", 32): 3,
+              ("combo", 16): 6, ("combo", 32): 6}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_traffic.json")
 TUNING_FILE = os.path.join(ROOT, "paper_1711_08475_amd", "tuned.json")
 MATCH_SRC = os.path.join(ROOT, "paper_1711_08475_amd", "csrc", "fpm_match.hip")

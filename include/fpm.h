@@ -71,7 +71,13 @@ typedef enum {
  * multiplicative hash); the symbol map is not used (fpm_num_fields = bits).
  * One edit replaces at most two bigrams, so F_D moves by at most 4 per edit
  * and a pair is rejected when F_D > 4k (Ham and Lev). */
-typedef enum { FPM_OCC = 0, FPM_COUNT = 1, FPM_POS = 2, FPM_OCCH = 3, FPM_QGRAM = 4 } fpm_variant;
+/* FPM_COMBO: occurrence and count combined in one word (Section 5 names
+ * combining fingerprint types as future work).  The low bits/2 bits are the
+ * occurrence fingerprint of fields 0 .. bits/2 - 1; above them, 2-bit
+ * saturating counters of fields 0 .. bits/4 - 1 (the map's first, most
+ * frequent fields).  F_D is the larger of the two parts' F_D (count part:
+ * L1), so Eq. 1 holds: a pair survives when both parts are <= 2k. */
+typedef enum { FPM_OCC = 0, FPM_COUNT = 1, FPM_POS = 2, FPM_OCCH = 3, FPM_QGRAM = 4, FPM_COMBO = 5 } fpm_variant;
 typedef enum { FPM_HAM = 0, FPM_LEV = 1 } fpm_metric;
 typedef enum { FPM_COMMON = 0, FPM_RARE = 1, FPM_MIXED = 2, FPM_CUSTOM = 3 } fpm_symbols;
 
@@ -151,8 +157,8 @@ void fpm_free(void *p);
 
 /* Number of symbol fields of a fingerprint (Section 3 variants with the
  * Section 4 parameters b = 2, p = 3): occ bits, occh bits/2, count bits/2,
- * pos bits/3 + bits%3, qgram bits (hash buckets).  Returns -1 for an unknown
- * variant or bits. */
+ * pos bits/3 + bits%3, qgram bits (hash buckets), combo bits/2.  Returns -1
+ * for an unknown variant or bits. */
 int fpm_num_fields(fpm_variant variant, uint32_t bits);
 
 /* Symbol selection (Section 3: common / rare / mixed sets).  A byte

@@ -59,6 +59,8 @@ int key_kind_for(int variant, uint32_t bits)
 {
     if (variant == FPM_QGRAM)
         return kQgram32;
+    if (variant == FPM_COMBO)
+        return kCombo64;
     if (variant == FPM_COUNT && bits == 32)
         return kPop64;
     if (variant == FPM_POS)
@@ -69,7 +71,7 @@ int key_kind_for(int variant, uint32_t bits)
 // Keys for the asymmetric bound; -1 where it is not defined (position).
 int key_kind_asym(int variant, uint32_t bits)
 {
-    if (variant == FPM_POS || variant == FPM_QGRAM)
+    if (variant == FPM_POS || variant == FPM_QGRAM || variant == FPM_COMBO)
         return -1;
     if (variant == FPM_COUNT)
         return bits == 32 ? kAsym64 : kAsym32;
@@ -301,6 +303,8 @@ int fpm_num_fields(fpm_variant variant, uint32_t bits)
         return (int)(bits / 3 + bits % 3);
     case FPM_QGRAM:
         return (int)bits;  // hash buckets; the symbol map is not used
+    case FPM_COMBO:
+        return (int)bits / 2;  // occurrence fields; the first bits/4 also count
     default:
         return -1;
     }

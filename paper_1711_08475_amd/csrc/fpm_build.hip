@@ -151,7 +151,10 @@ __global__ void k_layout(const uint8_t *bytes, const uint64_t *offsets, uint64_t
 // Bigram fingerprints (VARIANT 4, the q-gram direction of Section 5) ignore
 // the map: bigram (x, y) of the raw bytes sets bit
 // ((x * 256 + y) * 2654435761 mod 2^32) >> (32 - log2(bits)) (Knuth's
-// multiplicative hash); `aux` is log2(bits) for them and npos otherwise.
+// multiplicative hash).  Combined fingerprints (VARIANT 5, also Section 5):
+// occurrence bit f in the low bits/2 bits and, for f < bits/4, a 2-bit
+// saturating counter at bits/2 + 2f.  `aux` is log2(bits) for bigrams,
+// bits/2 for combined and npos otherwise.
 template <int VARIANT>
 __device__ __forceinline__ uint32_t fp_init(uint32_t npos)
 {
@@ -182,7 +185,12 @@ __device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t &prev, uint32_t 
         const uint32_t f = smap[(w >> (8 * j)) & 0xFFu];
         if (f == 0xFFu)
             continue;
-        if (VARIANT == 0) {
+        if (VARIANT == 5) {
+            fp |= 1u << f;
+            const uint32_t at = npos + 2 * f;
+            if (f < npos / 2 && ((fp >> at) & 3u) != 3u)
+                fp += 1u << at;
+        } else if (VARIANT == 0) {
             fp |= 1u << f;
         } else if (VARIANT == 3) {
             fp |= 1u << (2 * f + (pos >= half ? 1u : 0u));
@@ -203,7 +211,7 @@ __device__ __forceinline__ void fp_dword(uint32_t &fp, uint32_t &prev, uint32_t 
 template <int VARIANT>
 __device__ __forceinline__ uint32_t fp_aux(int bits)
 {
-    return VARIANT == 4 ? (bits == 16 ? 4u : 5u) : (uint32_t)bits / 3;
+    return VARIANT == 4 ? (bits == 16 ? 4u : 5u) : VARIANT == 5 ? (uint32_t)bits / 2 : (uint32_t)bits / 3;
 }
 
 template <int VARIANT>
@@ -218,7 +226,7 @@ __device__ __forceinline__ uint32_t fingerprint(const uint32_t *s, uint32_t L, c
 
 // Filter key of a fingerprint at sorted position p.
 template <int VARIANT>
-__device__ __forceinline__ void store_key(uint32_t fp, int key_kind, void *keys, uint32_t p)
+__device__ __forceinline__ void store_key(uint32_t fp, int key_kind, void *keys, uint32_t p, uint32_t aux)
 {
     if (VARIANT == 1) {
         // thermometer expansion of each 2-bit count v: [v>=1, v>=2, v>=3];
@@ -231,6 +239,14 @@ __device__ __forceinline__ void store_key(uint32_t fp, int key_kind, void *keys,
         } else {
             ((uint32_t *)keys)[p] = (t0 | (t1 << 1)) | (t2 << 16);  // 8 fields: bits 0..15 and 16..30
         }
+    } else if (key_kind == kCombo64) {
+        // occurrence half as it is (low word); the counters' thermometer
+        // expansion (as for count keys) in the high word
+        const uint32_t half = aux;  // bits / 2
+        const uint32_t occ = fp & ((1u << half) - 1u), c = fp >> half;
+        const uint32_t lo = c & 0x5555u, hi = (c >> 1) & 0x5555u;
+        const uint32_t th = (lo | hi) | (hi << 1) | ((lo & hi) << 16);
+        ((uint64_t *)keys)[p] = (uint64_t)occ | ((uint64_t)th << 32);
     } else if (key_kind == kTherm32) {
         // 16-bit fingerprint, thermometer code of its popcount above it
         ((uint32_t *)keys)[p] = fp | (((1u << __builtin_popcount(fp)) - 1u) << 16);
@@ -258,7 +274,7 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
     if (fp_orig)
         fp_orig[perm[p]] = fp;
     if (keys)
-        store_key<VARIANT>(fp, key_kind, keys, p);
+        store_key<VARIANT>(fp, key_kind, keys, p, aux);
 }
 
 // k_layout followed by the fingerprint of each string, built from the
@@ -307,7 +323,7 @@ __global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const u
     }
     if (fp_orig)
         fp_orig[i] = fp;
-    store_key<VARIANT>(fp, key_kind, keys, p);
+    store_key<VARIANT>(fp, key_kind, keys, p, npos);
 }
 
 // Reorder a laid-out set inside its length blocks by key popcount (stable):
@@ -476,8 +492,11 @@ void launch_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nb
     case 3:
         FPM_LAYOUT_FP(3);
         break;
-    default:
+    case 4:
         FPM_LAYOUT_FP(4);
+        break;
+    default:
+        FPM_LAYOUT_FP(5);
         break;
     }
 #undef FPM_LAYOUT_FP
@@ -506,8 +525,11 @@ void launch_fingerprints(const uint32_t *str, const uint32_t *soff, const uint8_
     case 3:
         FPM_FINGERPRINTS(3);
         break;
-    default:
+    case 4:
         FPM_FINGERPRINTS(4);
+        break;
+    default:
+        FPM_FINGERPRINTS(5);
         break;
     }
 #undef FPM_FINGERPRINTS

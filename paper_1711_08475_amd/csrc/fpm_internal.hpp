@@ -48,7 +48,10 @@ __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 //   Asym32 / Asym64: the Pop32 / Pop64 keys, tested as
 //            popc(~(q & w)) + max(pq, pw) against the key width + k + 1.
 // Qgram32: bigram fingerprints, F_D = popc(kq ^ kw) rejected above 4k (one
-// edit replaces at most two bigrams).
+// edit replaces at most two bigrams).  Combo64: combined occurrence + count
+// fingerprints, the occurrence half in the low word and the counters'
+// thermometer expansion in the high word; a pair survives when both words'
+// XOR popcounts are <= 2k.
 enum KeyKind : int {
     kPop32 = 0,
     kPop64 = 1,
@@ -58,10 +61,11 @@ enum KeyKind : int {
     kTherm32 = 5,
     kAsym32 = 6,
     kAsym64 = 7,
-    kQgram32 = 8
+    kQgram32 = 8,
+    kCombo64 = 9
 };
 
-__host__ __device__ inline bool key_is_64(int kind) { return kind == kPop64 || kind == kAsym64; }
+__host__ __device__ inline bool key_is_64(int kind) { return kind == kPop64 || kind == kAsym64 || kind == kCombo64; }
 
 struct StrSetView {
     const uint32_t *perm;  // sorted -> caller index

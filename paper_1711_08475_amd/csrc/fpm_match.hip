@@ -123,6 +123,19 @@ template <>
 struct Filter<kQgram32> : Filter<kPop32> {
 };
 
+// Combined fingerprints: each word's XOR popcount against 2k; the AND of the
+// two tests has its sign bit set iff both parts pass.
+template <>
+struct Filter<kCombo64> {
+    using Key = uint64_t;
+    static __device__ __forceinline__ uint32_t test(Key q, Key w, uint32_t neg)
+    {
+        const uint64_t x = q ^ w;
+        return ((uint32_t)__builtin_popcount((uint32_t)x) + neg) &
+               ((uint32_t)__builtin_popcount((uint32_t)(x >> 32)) + neg);
+    }
+};
+
 // Asymmetric bound on full-width keys: with c = popc(q & w) the larger
 // excess is max(pq, pw) - c, and it is <= k iff
 // popc(~(q & w)) + max(pq, pw) - (width + k + 1) < 0.  Each side's popcount
@@ -1043,6 +1056,8 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k
         return launch_kind<kAsym64>(a, metric, k, persistent, persistent_blocks, host_items, s);
     case kQgram32:
         return launch_kind<kQgram32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kCombo64:
+        return launch_kind<kCombo64>(a, metric, k, persistent, persistent_blocks, host_items, s);
     default:
         return launch_kind<kAll>(a, metric, k, persistent, persistent_blocks, host_items, s);
     }

@@ -20,12 +20,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfpm.so")
 
 FPM_OK, FPM_EINVAL, FPM_EUNSUPPORTED, FPM_ENOMEM, FPM_EDEVICE = 0, -1, -2, -3, -4
-FPM_OCC, FPM_COUNT, FPM_POS, FPM_OCCH, FPM_QGRAM = 0, 1, 2, 3, 4
+FPM_OCC, FPM_COUNT, FPM_POS, FPM_OCCH, FPM_QGRAM, FPM_COMBO = 0, 1, 2, 3, 4, 5
 FPM_HAM, FPM_LEV = 0, 1
 FPM_COMMON, FPM_RARE, FPM_MIXED, FPM_CUSTOM = 0, 1, 2, 3
 FPM_SCHED_PLAIN, FPM_SCHED_BATCHED, FPM_SCHED_BRUTE = 0, 1, 2
 
-VARIANTS = {"occ": FPM_OCC, "count": FPM_COUNT, "pos": FPM_POS, "occh": FPM_OCCH, "qgram": FPM_QGRAM}
+VARIANTS = {"occ": FPM_OCC, "count": FPM_COUNT, "pos": FPM_POS, "occh": FPM_OCCH, "qgram": FPM_QGRAM,
+            "combo": FPM_COMBO}
 METRICS = {"ham": FPM_HAM, "lev": FPM_LEV}
 SYMBOLS = {"common": FPM_COMMON, "rare": FPM_RARE, "mixed": FPM_MIXED, "custom": FPM_CUSTOM}
 FPM_BOUND_FD, FPM_BOUND_ASYM = 0, 1

@@ -52,5 +52,6 @@ def test_num_fields_without_gpu():
     assert [fpm.fpm_num_fields(v, 16) for v in ("occ", "count", "pos", "occh")] == [16, 8, 6, 8]
     assert [fpm.fpm_num_fields(v, 32) for v in ("occ", "count", "pos", "occh")] == [32, 16, 12, 16]
     assert fpm.fpm_num_fields("qgram", 16) == 16 and fpm.fpm_num_fields("qgram", 32) == 32
-    assert fpm.fpm_num_fields(5, 16) == -1
+    assert fpm.fpm_num_fields("combo", 16) == 8 and fpm.fpm_num_fields("combo", 32) == 16
+    assert fpm.fpm_num_fields(6, 16) == -1
     assert fpm.fpm_num_fields("occ", 8) == -1

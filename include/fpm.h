@@ -228,6 +228,9 @@ fpm_status fpm_verify_pairs(const fpm_index *ix, const uint8_t *qbytes, const ui
  * 255 or decreasing offsets are detected on the device and reported by
  * fpm_plan_result as FPM_EINVAL (those strings are clamped, never read out
  * of bounds: reads stay below qoffsets[n_queries] <= max_query_bytes).
+ * Plans are independent: two plans on two streams keep two batches in
+ * flight, and one batch's preparation and match-list sort then run beside
+ * the next batch's match kernel.
  * --------------------------------------------------------------------- */
 fpm_status fpm_plan_create(const fpm_index *ix, uint32_t max_queries, uint64_t max_query_bytes, fpm_metric metric,
                            uint32_t k, const fpm_options *opt, void *hip_stream, fpm_plan **out);

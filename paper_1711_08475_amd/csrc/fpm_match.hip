@@ -17,7 +17,11 @@
 // wave-uniform, loaded into scalar registers):
 //   t   = popcount(kq ^ kw) - (2k + 1)   one v_xor, one v_bcnt with accumulator
 //   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
-// i.e. three vector instructions per (query, word) pair.  Each of the lane's
+// i.e. three vector instructions per (query, word) pair (other key
+// families: position fields 8, bigrams 3 against 4k, the asymmetric bound 3
+// or 4, 64-bit keys 5 or 6).  Under the asymmetric bound the query and word
+// blocks are ordered by key popcount, and items and 32 x 128 passes whose
+// popcount ranges cannot meet are skipped.  Each of the lane's
 // two 32-bit survivor masks is then appended to a per-wave queue in LDS:
 // each lane with survivors reserves its range with one LDS atomic add on
 // the wave's queue counter (the LDS unit serialises the lanes, the VALU
@@ -56,8 +60,9 @@ constexpr int kOutCap = 95;
 constexpr int kOutFlush = kOutCap - 64;
 
 // -------------------------------------------------------------- filters
-// test() returns a value whose sign bit is set iff F_D <= 2k; `neg` holds
-// -(2k + 1).
+// test() returns a value whose sign bit is set iff the pair survives the
+// family's rule (F_D <= 2k for the paper's fingerprints); `neg` holds
+// filter_neg<KIND, K>() (-(2k + 1) for those).
 template <int KIND>
 struct Filter;
 

@@ -185,6 +185,13 @@ def test_empty_inputs(fpm):
     say("empty dictionary")
     ix0 = fpm.fpm_build_fingerprints(e, "occ", 16, "common")
     assert fpm.fpm_match(ix0, d, "lev", 1).shape == (0, 3)
+    for variant, bits in [("occ", 16), ("count", 32), ("qgram", 32), ("combo", 32)]:
+        say("empty dictionary", variant, bits)
+        ix0 = fpm.fpm_build_fingerprints(e, variant, bits, "common")
+        assert fpm.fpm_match(ix0, d, "lev", 3).shape == (0, 3)
+        if variant in ("occ", "count"):
+            assert fpm.fpm_match(ix0, d, "lev", 1, fpm.options(bound="asym")).shape == (0, 3)
+            assert fpm.fpm_match(ix, e, "lev", 1, fpm.options(bound="asym")).shape == (0, 3)
 
 
 def test_everything_survives_and_ragged_buckets(fpm):

@@ -185,8 +185,8 @@ def main():
                     help="first run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
-              f"MI355X; the design notes describe how queries would shard across GPUs)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one process drives one "
+              f"MI355X; sharding the query batch across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

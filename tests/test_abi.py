@@ -55,3 +55,15 @@ def test_num_fields_without_gpu():
     assert fpm.fpm_num_fields("combo", 16) == 8 and fpm.fpm_num_fields("combo", 32) == 16
     assert fpm.fpm_num_fields(6, 16) == -1
     assert fpm.fpm_num_fields("occ", 8) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with a message before any
+    device work."""
+    import subprocess
+    import sys as _sys
+
+    r = subprocess.run([_sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

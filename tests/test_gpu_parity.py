@@ -8,7 +8,8 @@ from paper_1711_08475_amd import datagen
 
 pytestmark = pytest.mark.gpu
 
-VARIANT_NAMES = {oracle.OCC: "occ", oracle.COUNT: "count", oracle.POS: "pos", oracle.OCCH: "occh"}
+VARIANT_NAMES = {oracle.OCC: "occ", oracle.COUNT: "count", oracle.POS: "pos", oracle.OCCH: "occh", oracle.QGRAM: "qgram",
+                 oracle.COMBO: "combo"}
 
 
 def say(*a):
@@ -122,13 +123,15 @@ def test_bruteforce_equals_oracle(fpm, small, metric, k):
 
 
 @pytest.mark.parametrize("variant,bits,metric,k", [(oracle.OCC, 16, oracle.LEV, 1), (oracle.COUNT, 32, oracle.LEV, 2),
-                                                   (oracle.POS, 16, oracle.HAM, 1)])
+                                                   (oracle.POS, 16, oracle.HAM, 1), (oracle.QGRAM, 32, oracle.LEV, 1),
+                                                   (oracle.COMBO, 32, oracle.LEV, 2), (oracle.OCCH, 32, oracle.HAM, 3)])
 def test_filter_survivor_set(fpm, small, variant, bits, metric, k):
     """The set of pairs the filter keeps equals {length-compatible pairs with
-    F_D <= 2k} computed from the oracle's fingerprints and F_D."""
+    F_D <= threshold (2k; bigrams 4k)} computed from the oracle's
+    fingerprints and F_D."""
     d, q = small
     q = datagen.take_csr(q, np.arange(200))
-    say("survivors", VARIANT_NAMES[variant], bits, metric, k)
+    say("survivors", VARIANT_NAMES.get(variant, variant), bits, metric, k)
     ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
     got = fpm.fpm_filter_pairs(ix, q, metric, k)
     mp = fpm.fpm_get_map(ix)
@@ -139,7 +142,7 @@ def test_filter_survivor_set(fpm, small, variant, bits, metric, k):
         gap = np.abs(lw - lq[i])
         cand = np.nonzero(gap == 0 if metric == oracle.HAM else gap <= k)[0]
         f = oracle.fd(np.full(cand.size, fq[i], dtype=np.uint32), fw[cand], variant, bits)
-        keep = cand[f <= 2 * k]
+        keep = cand[f <= oracle.threshold(variant, k)]
         rows.append(np.stack([np.full(keep.size, i), keep], axis=1))
     ref = np.concatenate(rows).astype(np.uint32)
     assert np.array_equal(got, ref)

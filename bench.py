@@ -163,7 +163,7 @@ def cpu_baseline(oracle, d, q, target_s: float, metric: int, k: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="english_1m_q10k")
     ap.add_argument("--variant", default="occ")

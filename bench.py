@@ -23,9 +23,10 @@ Forms timed on the same GPU:
                popcount-ordered blocks and popcount-range tile skipping.
 The headline is the paper's rule (learned); asym is reported beside it.
 
-Device-scheduled forms keep two batches in flight by default (--inflight):
-two plans, each with its own stream and buffers, take alternate steps, so one
-batch's preparation and match-list sort overlap the next batch's match
+Device-scheduled forms keep several batches in flight (two or three, chosen
+with the tiles and stored in the tuning table; --inflight overrides): that
+many plans, each with its own stream and buffers, take steps in turn, so one
+batch's preparation and match-list sort overlap another batch's match
 kernel.  Every step is still the whole pipeline over one batch; the kernel
 time in `roofline` is measured inside that timed, overlapped region.
 
@@ -89,15 +90,39 @@ def load_traffic(form: str, workload: str):
     return t
 
 
-def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int, bound: str = "fd"):
+def serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry):
+    """With several batches in flight the best slab shifts (the match kernel
+    shares the GPU with the other batches' small kernels): time the autotuned
+    tiles with 2 or 3 batches in flight and the slab or twice the slab, and
+    keep the fastest.  The persistent kernel keeps its full-GPU size, so one
+    launch still spans the whole GPU and its duration stays a measure of the
+    kernel.  Returns (entry, batches in flight)."""
+    best = None
+    for inflight in (2, 3):
+        for slab in sorted({entry["slab"], min(2 * entry["slab"], 1 << 22)}):
+            e = dict(entry, slab=slab)
+            plans = [fpm.fpm_plan_create(ix, nq, qbytes, metric, k, fpm.options(**e)) for _ in range(inflight)]
+            ms, _, _ = time_plans(fpm, torch, plans, qb, qo, nq, 100, 2)
+            del plans
+            if best is None or ms < best[0]:
+                best = (ms, e, inflight)
+    log(f"serving refinement: {best[2]} in flight, slab {best[1]['slab']}, {best[0]:.3f} ms/step")
+    return best[1], best[2]
+
+
+def tuned_options(fpm, torch, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int, bound: str = "fd"):
     """Autotuner result for `key`, from the tuning table when present (so a
     profiled run dispatches the match kernel with one configuration only),
-    else measured now and stored."""
+    else measured now and stored: fpm_autotune's tiles, then the serving
+    refinement (batches in flight, persistent waves, slab).  Returns
+    (options, batches in flight, tuned now)."""
     table = {}
     if os.path.exists(TUNING_FILE):
         table = json.load(open(TUNING_FILE))
     if key in table and not retune:
-        return fpm.options(**table[key]), False
+        entry = dict(table[key])
+        inflight = entry.pop("inflight", 2)
+        return fpm.options(**entry), inflight, False
     t = time.perf_counter()
     best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2,
                                   base=fpm.options(bound=bound))
@@ -105,10 +130,11 @@ def tuned_options(fpm, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k
         f"{sorted(rows, key=lambda r: r[4])[:4]}")
     entry = {k: v for k, v in best.as_dict().items()
              if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split", "bound")}
-    table[key] = entry
+    entry, inflight = serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry)
+    table[key] = dict(entry, inflight=inflight)
     with open(TUNING_FILE, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
-    return fpm.options(**entry), True
+    return fpm.options(**entry), inflight, True
 
 
 def time_plans(fpm, torch, plans, qb, qo, nq, steps, warmup):
@@ -178,9 +204,10 @@ def main():
     ap.add_argument("--train", action="store_true", help="train the learned grouping in this process")
     ap.add_argument("--no-autotune", action="store_true", help="default tiles for the batched form")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even when the table has an entry")
-    ap.add_argument("--inflight", type=int, default=2,
-                    help="batches in flight for the device-scheduled forms (one plan and stream each); the plain "
-                         "form reads its work list on the host every step and always runs one")
+    ap.add_argument("--inflight", type=int, default=0,
+                    help="batches in flight for the device-scheduled forms (one plan and stream each; default: the "
+                         "tuning table's choice for tuned forms, else 2); the plain form reads its work list on the "
+                         "host every step and always runs one")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -236,6 +263,7 @@ def main():
             log(f"trained grouping in {time.perf_counter() - t:.1f} s")
         indexes["learned"] = fpm.fpm_build_fingerprints(d, args.variant, args.bits, custom_map=mp)
     for mode in modes:
+        tuned_inflight = 2
         if mode == "plain":
             opts = fpm.options(schedule=fpm.FPM_SCHED_PLAIN, time_kernel=1)
         elif mode == "brute":
@@ -248,13 +276,14 @@ def main():
             else:
                 key = (f"{args.workload}|{args.variant}{args.bits}|{args.metric}{args.k}|"
                        f"{'common' if mode == 'batched' else 'learned'}" + ("|asym" if mode == "asym" else ""))
-                opts, fresh = tuned_options(fpm, key, mix, qb, qo, nq, qbytes, args.retune, args.metric, args.k,
-                                            bound)
-                log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {opts.as_dict()}")
+                opts, tuned_inflight, fresh = tuned_options(fpm, torch, key, mix, qb, qo, nq, qbytes, args.retune,
+                                                            args.metric, args.k, bound)
+                log(f"{mode} tiles ({'autotuned now' if fresh else 'tuning table'}): {opts.as_dict()}, "
+                    f"{tuned_inflight} in flight")
                 opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
-        inflight = 1 if mode == "plain" else max(1, args.inflight)
+        inflight = 1 if mode == "plain" else (args.inflight if args.inflight > 0 else tuned_inflight)
         plans = [fpm.fpm_plan_create(indexes["paper" if mode in ("plain", "brute", "batched") else "learned"], nq,
                                      qbytes, args.metric, args.k, opts) for _ in range(inflight)]
         ms, n, st = time_plans(fpm, torch, plans, qb, qo, nq, args.steps, args.warmup)

@@ -421,7 +421,8 @@ struct ByteStream {
 };
 
 // Banded edit distance (Ukkonen's cut-off: only |j - i| <= K matters when
-// the distance is at most K), values saturated at K + 1.  Row i keeps cells
+// the distance is at most K), cells outside the band held at K + 1, the
+// result capped at K + 1.  Row i keeps cells
 // j = i - K .. i + K; `win` holds the symbols b[j - 1] those cells compare,
 // byte t for j = i + t - K.
 template <int K>
@@ -456,11 +457,16 @@ __device__ __forceinline__ uint32_t verify_lev_band(const uint32_t *a, uint32_t 
             } else if (j == 0) {
                 v = min(i, INF);
             } else {
-                const uint32_t bj = (uint32_t)(win >> (8 * t)) & 0xFFu;
+                // a byte field extract lets the compare read the byte in place
+                const uint32_t bj =
+                    __builtin_amdgcn_ubfe(t < 4 ? (uint32_t)win : (uint32_t)(win >> 32), 8u * (uint32_t)(t & 3), 8u);
+                // no clamp at INF: cells outside the band enter as INF, so any
+                // value computed through them exceeds k, and values <= k are
+                // exact (Ukkonen's band); the result is clamped at the end
                 const uint32_t diag = prev[t] + (ai != bj ? 1u : 0u);
                 const uint32_t up = (t + 1 < W) ? prev[t + 1] + 1u : INF;
                 const uint32_t left = (t >= 1) ? cur[t - 1] + 1u : INF;
-                v = min(min(diag, up), min(left, INF));
+                v = min(min(diag, up), left);
             }
             cur[t] = v;
             rowmin = min(rowmin, v);

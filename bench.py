@@ -208,6 +208,9 @@ def main():
                     help="batches in flight for the device-scheduled forms (one plan and stream each; default: the "
                          "tuning table's choice for tuned forms, else 2); the plain form reads its work list on the "
                          "host every step and always runs one")
+    ap.add_argument("--filter-unit", default="auto", choices=["auto", "valu", "matrix"],
+                    help="where the filter test runs: auto (matrix cores for 16-bit occurrence, "
+                         "occurrence-halved and bigram keys under the paper's rule, else vector ALUs), valu, matrix")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -283,6 +286,8 @@ def main():
                 opts.time_kernel = 1
         else:
             raise SystemExit(f"unknown mode {mode}")
+        if not (args.filter_unit == "matrix" and mode in ("asym", "brute")):
+            opts.filter_unit = fpm.UNITS[args.filter_unit]
         inflight = 1 if mode == "plain" else (args.inflight if args.inflight > 0 else tuned_inflight)
         plans = [fpm.fpm_plan_create(indexes["paper" if mode in ("plain", "brute", "batched") else "learned"], nq,
                                      qbytes, args.metric, args.k, opts) for _ in range(inflight)]

@@ -107,6 +107,26 @@ typedef enum { FPM_SCHED_PLAIN = 0, FPM_SCHED_BATCHED = 1, FPM_SCHED_BRUTE = 2 }
  *     Matches are the same under both rules; survivors differ. */
 typedef enum { FPM_BOUND_FD = 0, FPM_BOUND_ASYM = 1 } fpm_bound;
 
+/* Where the filter test F_D <= t (Eq. 1; t = 2k, bigrams 4k) runs.
+ *   FPM_UNIT_AUTO (default): on the matrix cores where the key family
+ *     allows it, else on the vector ALUs.
+ *   FPM_UNIT_VALU: vector ALUs only -- per pair one XOR, one popcount and
+ *     one shift of the result's sign bit into a survivor mask.
+ *   FPM_UNIT_MATRIX: matrix cores; FPM_EUNSUPPORTED where the key family
+ *     does not allow it.  F_D of two bit vectors is an inner product: with
+ *     every key bit written as a signed byte (+1 for 0, -1 for 1 on the
+ *     query side, the negation on the word side), the product of a query
+ *     row and a word column over the W key positions is 2 F_D - W.  One
+ *     8-bit integer matrix instruction (32 x 32 outputs, K = W = 16 or 32)
+ *     adds W - 2t - 1 and yields 2 F_D - 2t - 1 for 1,024 pairs, negative
+ *     exactly when the pair survives; the sign bits go into the same
+ *     survivor masks as on the vector path.  Offered for the paper's rule
+ *     (FPM_BOUND_FD) on keys of up to 32 bits whose F_D is the popcount of
+ *     their XOR: occurrence, occurrence-halved and 16-bit count
+ *     fingerprints, and bigrams.  Survivors and matches are the same on
+ *     both units. */
+typedef enum { FPM_UNIT_AUTO = 0, FPM_UNIT_VALU = 1, FPM_UNIT_MATRIX = 2 } fpm_filter_unit;
+
 /* One reported match.  `query` and `word` index the caller's lists. */
 typedef struct {
     uint32_t query;
@@ -143,7 +163,8 @@ typedef struct {
                                   at least 16 by 64), listed after every full-size item so that a launch
                                   ends on short items; 0 = default (100: no tail items) */
     uint32_t bound;            /* fpm_bound: filter rule (default FPM_BOUND_FD); ignored by FPM_SCHED_BRUTE */
-    uint32_t reserved[6];
+    uint32_t filter_unit;      /* fpm_filter_unit: where the filter test runs (default FPM_UNIT_AUTO) */
+    uint32_t reserved[5];
 } fpm_options;
 
 typedef struct fpm_index fpm_index;

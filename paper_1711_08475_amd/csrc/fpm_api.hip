@@ -221,6 +221,8 @@ struct fpm_plan {
     int kind = kPop32;
     bool asym = false;  // asymmetric bound: query blocks ordered by popcount too
     bool survivors_only = false;
+    int mx_width = 0;         // matrix-core filter over keys of this many bits (0: vector ALUs)
+    uint8_t *qexp = nullptr;  // its query rows (kMxRowBytes each, 64 padding rows)
 
     StrSet q;
     // asymmetric bound: the dictionary with every length block ordered by
@@ -515,6 +517,7 @@ static void plan_free(fpm_plan *p)
     dfree(p->keys);
     dfree(p->tmp);
     dfree(p->triples);
+    dfree(p->qexp);
     if (p->ev0)
         (void)hipEventDestroy(p->ev0);
     if (p->ev1)
@@ -570,6 +573,8 @@ static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
         return fail(FPM_EINVAL, "tail_split must be in 1..100 (0 = default)");
     if (o->bound > FPM_BOUND_ASYM)
         return fail(FPM_EINVAL, "unknown bound %u", o->bound);
+    if (o->filter_unit > FPM_UNIT_MATRIX)
+        return fail(FPM_EINVAL, "unknown filter unit %u", o->filter_unit);
     return FPM_OK;
 }
 
@@ -637,6 +642,16 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
                                       "fingerprints only");
     }
     p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : p->asym ? ix->kind_asym : ix->kind;
+    // the matrix-core filter: the paper's rule on 16-bit keys whose F_D is
+    // the popcount of their XOR
+    const bool mx_ok = !p->asym && (p->kind == kPop32 || p->kind == kQgram32) && ix->bits == 16 &&
+                       ix->variant != FPM_COUNT;
+    if (p->opt.filter_unit == FPM_UNIT_MATRIX && !mx_ok) {
+        delete p;
+        return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on 16-bit occurrence, "
+                                      "occurrence-halved and bigram fingerprints");
+    }
+    p->mx_width = mx_ok && p->opt.filter_unit != FPM_UNIT_VALU ? 16 : 0;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;
@@ -650,6 +665,13 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         (e = dalloc(&p->ctr, 1)) || (e = hipEventCreate(&p->ev0)) || (e = hipEventCreate(&p->ev1))) {
         plan_free(p);
         return hip_fail(e, "fpm_plan_create alloc");
+    }
+    if (p->mx_width) {
+        const size_t qb = ((size_t)max_queries + 64) * kMxRowBytes;
+        if ((e = dalloc(&p->qexp, qb)) || (e = hipMemset(p->qexp, 0, qb))) {
+            plan_free(p);
+            return hip_fail(e, "fpm_plan_create alloc");
+        }
     }
     p->q.pop_ordered = p->asym;
     st = p->alloc_output(p->opt.match_capacity);
@@ -697,6 +719,10 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     const bool fps = p->kind != kAll;
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
                  fps ? p->kind : kPop32, fps, p->asym, &p->ctr->err, p->scratch, s);
+    if (p->mx_width) {
+        const uint32_t t = p->kind == kQgram32 ? 4 * p->k : 2 * p->k;  // the F_D threshold
+        launch_expand_keys((const uint32_t *)p->q.key, nq, p->mx_width, t, p->qexp, s);
+    }
     if (plain) {
         uint32_t h_qoff[257];
         HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));
@@ -734,8 +760,9 @@ static fpm_status enqueue_kernel(fpm_plan *p, bool plain)
     a.out_cap = p->cap;
     a.wbits = ix->wbits;
     a.survivors_only = p->survivors_only ? 1u : 0u;
-    hipError_t e =
-        launch_match(a, p->kind, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks, p->host_items, p->stream);
+    a.qexp = p->qexp;
+    hipError_t e = launch_match(a, p->kind, p->mx_width, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks,
+                                p->host_items, p->stream);
     if (e)
         return hip_fail(e, "match kernel launch");
     return FPM_OK;

@@ -121,6 +121,9 @@ struct MatchArgs {
     uint64_t out_cap;
     uint32_t wbits;       // bits of a word index in the packed key
     uint32_t survivors_only;  // 1: report every survivor with dist 0, no verification
+    // matrix-core filter: the query keys as signed bytes (launch_expand_keys),
+    // key_width bytes per sorted query, 64 padding rows
+    const uint8_t *qexp;
 };
 
 // ----------------------------------------------------------------- build
@@ -187,8 +190,18 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
 //   persistent: grid = persistent_blocks; wave w takes item w first, then
 //   items from the striped counters;
 //   otherwise grid covers host_items items, one per wave.
-hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,
+//   key_width 16: the filter test runs on the matrix cores over 16-bit keys
+//   (key kinds kPop32 and kQgram32 only; a.qexp filled by
+//   launch_expand_keys); 0: on the vector ALUs.
+hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s);
+
+// Query side of the matrix-core filter: each of the n 16-bit keys becomes a
+// kMxRowBytes-byte row of signed bytes (+1 for a clear bit, -1 for a set
+// bit) with the threshold byte 2t - 15 (t: the family's F_D threshold,
+// at most 15); width must be 16.
+constexpr int kMxRowBytes = 32;
+void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s);
 
 // Exact distances of explicit (query, word) pairs given as caller indices;
 // qinv / dinv map caller index -> sorted position.

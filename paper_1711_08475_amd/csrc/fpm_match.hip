@@ -600,6 +600,141 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     }
 }
 
+// Append one lane's survivor mask to the wave queue: bit b is the entry
+// ent0 + (b << kWordBits).  Each lane with survivors reserves its range with
+// one LDS atomic on the wave's counter.  The caller drains the queue, 64
+// entries at a time, after the pass's masks are in (one drain site per pass
+// keeps the verifier's registers out of the filter loop).  When the wave's
+// survivors would overflow the queue the mask goes in as two 16-bit halves
+// with drains in between.
+template <int METRIC, int K>
+__device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint32_t *queue, uint32_t *qcnt,
+                                       uint32_t &qlen, uint32_t msk, uint32_t ent0, uint32_t lane,
+                                       uint64_t &survivors, uint64_t &cells, uint64_t *out, uint32_t &ocount)
+{
+    const uint32_t c = (uint32_t)__builtin_popcount(msk);
+    if (!__ballot(c != 0))
+        return;
+    if (lane == 0)
+        *qcnt = qlen;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t pos = 0;
+    if (c)
+        pos = atomicAdd(qcnt, c);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t tot = __builtin_amdgcn_readfirstlane(*qcnt);
+    if (tot <= (uint32_t)kQueueCap) {
+        while (msk) {
+            const uint32_t bit = (uint32_t)__builtin_ctz(msk);
+            queue[pos++] = ent0 + (bit << kWordBits);
+            msk &= msk - 1u;
+        }
+        __builtin_amdgcn_wave_barrier();
+        survivors += tot - qlen;
+        qlen = tot;
+        return;
+    }
+    // more survivors than the queue holds (nothing was written): one half at
+    // a time, each appended to a queue drained below 64 entries, so that
+    // at most 63 + 64 * 16 = kQueueCap entries are held
+    for (uint32_t h = 0; h < 2; ++h) {
+        while (qlen >= 64)
+            drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+        uint32_t m = h ? (msk >> kChunk) : (msk & 0xFFFFu);
+        const uint32_t ch = (uint32_t)__builtin_popcount(m);
+        if (!__ballot(ch != 0))
+            continue;
+        if (lane == 0)
+            *qcnt = qlen;
+        __builtin_amdgcn_wave_barrier();
+        uint32_t p = 0;
+        if (ch)
+            p = atomicAdd(qcnt, ch);
+        const uint32_t e1 = ent0 + ((h * kChunk) << kWordBits);
+        while (m) {
+            const uint32_t bit = (uint32_t)__builtin_ctz(m);
+            queue[p++] = e1 + (bit << kWordBits);
+            m &= m - 1u;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t nlen = __builtin_amdgcn_readfirstlane(*qcnt);
+        survivors += nlen - qlen;
+        qlen = nlen;
+    }
+}
+
+// ------------------------------------------------------- matrix filter
+// F_D = popc(q ^ w) of 16-bit keys as an 8-bit integer contraction on the
+// matrix cores (v_mfma_i32_32x32x32_i8: D = A B + C, A 32 x 32 query rows,
+// B 32 x 32 word columns).  Key bit j is a signed byte: 1 - 2 q_j on the
+// query side and 2 w_j - 1 on the word side, so the 16 key positions of a
+// row-column product sum to 2 F_D - 16.  The contraction has 32 positions:
+// a lane half h (lanes 32h .. 32h + 31) holds positions 16h .. 16h + 15 of
+// its row / column, and the key occupies the first 8 of them (bits 8h ..
+// 8h + 7).  Position 8 carries the threshold: the query row holds
+// 2t - 15 there (t = 2k, 4k for bigrams) and every word column -1 (word
+// columns are -1 at all eight spare positions, the bytes of the key's
+// clear upper bits); the query row is zero at the other spare positions.
+// Each output is then 2 F_D - 2t - 1, negative iff F_D <= t, with the
+// accumulator input C = 0 (an inline constant: no register tile).
+//
+// Output layout: lane l holds column l % 32 and, in its 16 result
+// registers r, rows 8 (r / 4) + 4 (l / 32) + r % 4.  Query rows are loaded
+// in a permuted order so that result register r of lane half h of the
+// pass's tile t (0, 1) is query 32 h + 16 t + r: row i of tile t holds query
+// 32 ((i / 4) % 2) + 16 t + 4 (i / 8) + i % 4.  Shifting the sign bits of
+// tile 1's registers 15 .. 0 and then tile 0's into a mask gives bit b =
+// query 32 h + b, the vector path's mask layout with 64 queries per pass.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+// Four key bits -> four bytes: byte i is byte 0 of if_set where bit i is
+// set, else byte 0 of if_clear (v_perm_b32 selector 4 picks byte 0 of its
+// first operand, selector 0 byte 0 of its second).
+__device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t if_set, uint32_t if_clear)
+{
+    const uint32_t sel = __umul24(nib, 0x00810204u) & 0x04040404u;  // bit i -> byte i = 4 * bit
+    return __builtin_amdgcn_perm(if_set, if_clear, sel);
+}
+
+// The lane's word column fragment: key bits 8h .. 8h + 7 as bytes 0 .. 7
+// (word_bytes: two dwords), then -1s (position 8 meets the threshold byte
+// of the query rows).
+struct WordBytes {
+    uint32_t lo, hi;
+};
+__device__ __forceinline__ WordBytes word_bytes(uint32_t w, uint32_t h)
+{
+    const uint32_t x = w >> (8u * h);
+    return WordBytes{nibble_bytes(x & 15u, 0x01010101u, 0xFFFFFFFFu),
+                     nibble_bytes((x >> 4) & 15u, 0x01010101u, 0xFFFFFFFFu)};
+}
+__device__ __forceinline__ v4i_t word_fragment(WordBytes b)
+{
+    // assembled per pass: a fragment kept live across the queue drains
+    // would hold four registers there instead of two; the -1s are made in
+    // the loop too (hoisted, they sit in scalar registers that the drains
+    // then spill)
+    uint32_t m1 = ~0u;
+    asm volatile("" : "+v"(b.lo), "+v"(b.hi), "+v"(m1));
+    v4i_t f;
+    f[0] = (int)b.lo;
+    f[1] = (int)b.hi;
+    f[2] = (int)m1;
+    f[3] = (int)m1;
+    return f;
+}
+
+// One 32 x 32 tile: shift the 16 sign bits of the lane's results into m,
+// register 15 first.
+__device__ __forceinline__ void mx_tile(v4i_t qa, v4i_t wb, uint32_t &m)
+{
+    const v16i_t d = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa, wb, (v16i_t)(0), 0, 0, 0);
+#pragma unroll
+    for (int r = 15; r >= 0; --r)
+        m = __builtin_amdgcn_alignbit(m, (uint32_t)d[r], 31);
+}
+
 // ------------------------------------------------------------ schedule
 
 // Issue priority follows the item's position in the work list, so items
@@ -652,7 +787,7 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, u
     return n_items;
 }
 
-template <int KIND, int METRIC, int K, bool PERSISTENT>
+template <int KIND, int METRIC, int K, bool PERSISTENT, bool MX>
 __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 {
     using F = Filter<KIND>;
@@ -693,102 +828,95 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                 it.de = it.ds;
         }
         uint32_t qlen = 0;
-        // two words per lane: words e0 + lane and e0 + 64 + lane
-        Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
-        Key wb_next = (it.ds + 64 + lane < it.de) ? dkeys[it.ds + 64 + lane] : Key(0);
-        for (uint32_t e0 = it.ds; e0 < it.de; e0 += 128) {
-            const Key wa = wa_next, wb = wb_next;
-            wa_next = (e0 + 128 + lane < it.de) ? dkeys[e0 + 128 + lane] : Key(0);
-            wb_next = (e0 + 192 + lane < it.de) ? dkeys[e0 + 192 + lane] : Key(0);
-            uint32_t glo = 0, ghi = 0;
-            if constexpr (kSkip) {
-                // popcount range of this group of 128 words (ascending)
-                const uint32_t last = min(e0 + 127u, it.de - 1u) - e0;
-                glo = key_pop(lane_key(wa, 0));
-                ghi = key_pop(last >= 64u ? lane_key(wb, last - 64u) : lane_key(wa, last));
-            }
-            uint32_t sa = 0, sb = 0;
-            if constexpr (side_values<KIND>()) {
-                sa = F::side_w(wa, neg);
-                sb = F::side_w(wb, neg);
-            }
-            for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
-                const uint32_t nqc = min(2u * kChunk, it.qn - j0);
-                const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
-                if constexpr (kSkip) {
-                    if (pop_apart(key_pop(qk[0]), key_pop(qk[nqc - 1]), glo, ghi, kGap))
-                        continue;
-                }
-                uint32_t ma = 0, mb = 0;
-                if (nqc > (uint32_t)kChunk) {
-#pragma unroll
-                    for (int t = 2 * kChunk - 1; t >= kChunk; --t)
-                        filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
-                }
-#pragma unroll
-                for (int t = kChunk - 1; t >= 0; --t)
-                    filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
-                // bit t <-> query j0 + t; drop the padding queries
-                // and the lanes past the slab (only on the item's ragged edges)
-                if (nqc < 2u * kChunk || e0 + 128 > it.de) {
-                    const uint32_t qm = nqc < 32u ? (1u << nqc) - 1u : ~0u;
-                    ma = (e0 + lane < it.de) ? ma & qm : 0u;
-                    mb = (e0 + 64 + lane < it.de) ? mb & qm : 0u;
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < 2; ++u) {
-                    uint32_t msk = u ? mb : ma;
-                    const uint32_t e = e0 + 64 * u + lane;
-                    const uint32_t c = (uint32_t)__builtin_popcount(msk);
-                    if (!__ballot(c != 0))
-                        continue;
-                    if (lane == 0)
-                        qcount[wave] = qlen;
-                    __builtin_amdgcn_wave_barrier();
-                    uint32_t pos = 0;
-                    if (c)
-                        pos = atomicAdd(&qcount[wave], c);
-                    __builtin_amdgcn_wave_barrier();
-                    const uint32_t tot = __builtin_amdgcn_readfirstlane(qcount[wave]);
-                    const uint32_t ent0 = (j0 << kWordBits) | (e - it.ds);
-                    if (tot <= (uint32_t)kQueueCap) {
-                        while (msk) {
-                            const uint32_t bit = (uint32_t)__builtin_ctz(msk);
-                            queue[pos++] = ent0 + (bit << kWordBits);
-                            msk &= msk - 1u;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        survivors += tot - qlen;
-                        qlen = tot;
-                        while (qlen >= 64)
-                            drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
-                    } else {
-                        // more survivors than the queue holds: one half at a time
-                        for (uint32_t h = 0; h < 2; ++h) {
-                            uint32_t m = h ? (msk >> kChunk) : (msk & 0xFFFFu);
-                            const uint32_t ch = (uint32_t)__builtin_popcount(m);
-                            if (!__ballot(ch != 0))
-                                continue;
-                            if (lane == 0)
-                                qcount[wave] = qlen;
-                            __builtin_amdgcn_wave_barrier();
-                            uint32_t p = 0;
-                            if (ch)
-                                p = atomicAdd(&qcount[wave], ch);
-                            const uint32_t e1 = ent0 + ((h * kChunk) << kWordBits);
-                            while (m) {
-                                const uint32_t bit = (uint32_t)__builtin_ctz(m);
-                                queue[p++] = e1 + (bit << kWordBits);
-                                m &= m - 1u;
-                            }
-                            __builtin_amdgcn_wave_barrier();
-                            const uint32_t nlen = __builtin_amdgcn_readfirstlane(qcount[wave]);
-                            survivors += nlen - qlen;
-                            qlen = nlen;
-                            while (qlen >= 64)
-                                drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
-                        }
+        if constexpr (MX) {
+            // matrix cores: 64 queries x 64 words per pass, the lane's words
+            // e0 + lane % 32 and e0 + 32 + lane % 32, queries 32 (lane / 32) + b
+            const uint32_t h = lane >> 5, col = lane & 31u;
+            const uint32_t qrow = 32u * ((col >> 2) & 1u) + 4u * (col >> 3) + (col & 3u);
+            const uint32_t qoff = qrow * kMxRowBytes + 16u * h;  // the lane's fragment in a 64-row block
+            uint32_t wa_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
+            uint32_t wb_next = (it.ds + 32 + col < it.de) ? dkeys[it.ds + 32 + col] : 0u;
+            for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
+                const WordBytes xa = word_bytes(wa_next, h), xb = word_bytes(wb_next, h);
+                wa_next = (e0 + 64 + col < it.de) ? dkeys[e0 + 64 + col] : 0u;
+                wb_next = (e0 + 96 + col < it.de) ? dkeys[e0 + 96 + col] : 0u;
+                for (uint32_t j0 = 0; j0 < it.qn; j0 += 64) {
+                    const v4i_t ba = word_fragment(xa), bb = word_fragment(xb);
+                    // rows qs + j0 + 63 at most: the expanded rows carry 64 padding rows
+                    const uint8_t *qb = a.qexp + (size_t)(it.qs + j0) * kMxRowBytes;
+                    const v4i_t q0 = *(const v4i_t *)(qb + qoff);
+                    const v4i_t q1 = *(const v4i_t *)(qb + qoff + 16u * kMxRowBytes);
+                    uint32_t ma = 0, mb = 0;
+                    mx_tile(q1, ba, ma);
+                    mx_tile(q0, ba, ma);
+                    mx_tile(q1, bb, mb);
+                    mx_tile(q0, bb, mb);
+                    const uint32_t nqc = min(64u, it.qn - j0);
+                    if (nqc < 64u || e0 + 64 > it.de) {
+                        const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
+                        const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
+                        ma = (e0 + col < it.de) ? ma & qm : 0u;
+                        mb = (e0 + 32 + col < it.de) ? mb & qm : 0u;
                     }
+                    const uint32_t ent0 = ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds);
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, survivors, cells, out,
+                                      ocount);
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, survivors, cells,
+                                      out, ocount);
+                    while (qlen >= 64)
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                }
+            }
+        } else {
+            // two words per lane: words e0 + lane and e0 + 64 + lane
+            Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
+            Key wb_next = (it.ds + 64 + lane < it.de) ? dkeys[it.ds + 64 + lane] : Key(0);
+            for (uint32_t e0 = it.ds; e0 < it.de; e0 += 128) {
+                const Key wa = wa_next, wb = wb_next;
+                wa_next = (e0 + 128 + lane < it.de) ? dkeys[e0 + 128 + lane] : Key(0);
+                wb_next = (e0 + 192 + lane < it.de) ? dkeys[e0 + 192 + lane] : Key(0);
+                uint32_t glo = 0, ghi = 0;
+                if constexpr (kSkip) {
+                    // popcount range of this group of 128 words (ascending)
+                    const uint32_t last = min(e0 + 127u, it.de - 1u) - e0;
+                    glo = key_pop(lane_key(wa, 0));
+                    ghi = key_pop(last >= 64u ? lane_key(wb, last - 64u) : lane_key(wa, last));
+                }
+                uint32_t sa = 0, sb = 0;
+                if constexpr (side_values<KIND>()) {
+                    sa = F::side_w(wa, neg);
+                    sb = F::side_w(wb, neg);
+                }
+                for (uint32_t j0 = 0; j0 < it.qn; j0 += 2 * kChunk) {
+                    const uint32_t nqc = min(2u * kChunk, it.qn - j0);
+                    const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
+                    if constexpr (kSkip) {
+                        if (pop_apart(key_pop(qk[0]), key_pop(qk[nqc - 1]), glo, ghi, kGap))
+                            continue;
+                    }
+                    uint32_t ma = 0, mb = 0;
+                    if (nqc > (uint32_t)kChunk) {
+#pragma unroll
+                        for (int t = 2 * kChunk - 1; t >= kChunk; --t)
+                            filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
+                    }
+#pragma unroll
+                    for (int t = kChunk - 1; t >= 0; --t)
+                        filter_step<KIND>(qk[t], wa, wb, sa, sb, neg, ma, mb);
+                    // bit t <-> query j0 + t; drop the padding queries
+                    // and the lanes past the slab (only on the item's ragged edges)
+                    if (nqc < 2u * kChunk || e0 + 128 > it.de) {
+                        const uint32_t qm = nqc < 32u ? (1u << nqc) - 1u : ~0u;
+                        ma = (e0 + lane < it.de) ? ma & qm : 0u;
+                        mb = (e0 + 64 + lane < it.de) ? mb & qm : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < 2; ++u)
+                        append<METRIC, K>(a, it, queue, &qcount[wave], qlen, u ? mb : ma,
+                                          (j0 << kWordBits) | (e0 + 64 * u + lane - it.ds), lane, survivors, cells, out,
+                                          ocount);
+                    while (qlen >= 64)
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
                 }
             }
         }
@@ -971,36 +1099,59 @@ __global__ void k_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
     dist[i] = verify<METRIC, K>(q.str + q.soff[qi], q.len[qi], d.str + d.soff[wi], d.len[wi]);
 }
 
-template <int KIND, int METRIC, int K>
+template <int KIND, int METRIC, int K, bool MX = false>
 hipError_t launch_kmk(const MatchArgs &a, bool persistent, uint32_t pblocks, uint32_t host_items, hipStream_t s)
 {
     if (persistent) {
-        hipLaunchKernelGGL((k_match<KIND, METRIC, K, true>), dim3(pblocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_match<KIND, METRIC, K, true, MX>), dim3(pblocks), dim3(256), 0, s, a);
     } else {
         if (host_items == 0)
             return hipSuccess;
-        hipLaunchKernelGGL((k_match<KIND, METRIC, K, false>), dim3((host_items + kWaves - 1) / kWaves), dim3(256), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_match<KIND, METRIC, K, false, MX>), dim3((host_items + kWaves - 1) / kWaves), dim3(256),
+                           0, s, a);
     }
     return hipGetLastError();
 }
 
-template <int KIND>
+template <int KIND, bool MX = false>
 hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persistent, uint32_t pblocks,
                        uint32_t host_items, hipStream_t s)
 {
     if (metric == 0) {
         if (k == 1)
-            return launch_kmk<KIND, 0, 1>(a, persistent, pblocks, host_items, s);
+            return launch_kmk<KIND, 0, 1, MX>(a, persistent, pblocks, host_items, s);
         if (k == 2)
-            return launch_kmk<KIND, 0, 2>(a, persistent, pblocks, host_items, s);
-        return launch_kmk<KIND, 0, 3>(a, persistent, pblocks, host_items, s);
+            return launch_kmk<KIND, 0, 2, MX>(a, persistent, pblocks, host_items, s);
+        return launch_kmk<KIND, 0, 3, MX>(a, persistent, pblocks, host_items, s);
     }
     if (k == 1)
-        return launch_kmk<KIND, 1, 1>(a, persistent, pblocks, host_items, s);
+        return launch_kmk<KIND, 1, 1, MX>(a, persistent, pblocks, host_items, s);
     if (k == 2)
-        return launch_kmk<KIND, 1, 2>(a, persistent, pblocks, host_items, s);
-    return launch_kmk<KIND, 1, 3>(a, persistent, pblocks, host_items, s);
+        return launch_kmk<KIND, 1, 2, MX>(a, persistent, pblocks, host_items, s);
+    return launch_kmk<KIND, 1, 3, MX>(a, persistent, pblocks, host_items, s);
+}
+
+// Query rows of the matrix filter: key bits 0 .. 7 as bytes 0 .. 7, the
+// threshold byte 2t - 15 at 8, bits 8 .. 15 as bytes 16 .. 23, zeros
+// elsewhere (1 - 2 q_j: 0x01 for a clear bit, 0xFF for a set bit).
+__global__ void k_expand_keys(const uint32_t *keys, uint32_t n, uint32_t t, uint8_t *out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t w = keys[i];
+    uint4 lo, hi;
+    lo.x = nibble_bytes(w & 15u, 0xFFFFFFFFu, 0x01010101u);
+    lo.y = nibble_bytes((w >> 4) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    lo.z = (2u * t - 15u) & 0xFFu;
+    lo.w = 0u;
+    hi.x = nibble_bytes((w >> 8) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    hi.y = nibble_bytes((w >> 12) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    hi.z = 0u;
+    hi.w = 0u;
+    uint4 *row = (uint4 *)(out + (size_t)i * kMxRowBytes);
+    row[0] = lo;
+    row[1] = hi;
 }
 
 }  // namespace
@@ -1039,9 +1190,25 @@ void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uin
     hipLaunchKernelGGL(k_worklist, dim3(1), dim3(256), 0, s, qoff, doff, metric, k, qtile, slab, order, tail_pct, wl);
 }
 
-hipError_t launch_match(const MatchArgs &a, int key_kind, int metric, uint32_t k, bool persistent,
+void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s)
+{
+    (void)width;  // 16-bit keys: one row layout
+    if (n)
+        hipLaunchKernelGGL(k_expand_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, t, out);
+}
+
+hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s)
 {
+    if (key_width) {
+        if (key_width != 16)
+            return hipErrorInvalidValue;
+        if (key_kind == kPop32)
+            return launch_kind<kPop32, true>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        if (key_kind == kQgram32)
+            return launch_kind<kQgram32, true>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        return hipErrorInvalidValue;
+    }
     switch (key_kind) {
     case kPop32:
         return launch_kind<kPop32>(a, metric, k, persistent, persistent_blocks, host_items, s);

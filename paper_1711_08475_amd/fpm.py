@@ -31,6 +31,8 @@ METRICS = {"ham": FPM_HAM, "lev": FPM_LEV}
 SYMBOLS = {"common": FPM_COMMON, "rare": FPM_RARE, "mixed": FPM_MIXED, "custom": FPM_CUSTOM}
 FPM_BOUND_FD, FPM_BOUND_ASYM = 0, 1
 BOUNDS = {"fd": FPM_BOUND_FD, "asym": FPM_BOUND_ASYM}
+FPM_UNIT_AUTO, FPM_UNIT_VALU, FPM_UNIT_MATRIX = 0, 1, 2
+UNITS = {"auto": FPM_UNIT_AUTO, "valu": FPM_UNIT_VALU, "matrix": FPM_UNIT_MATRIX}
 
 # every symbol include/fpm.h declares
 EXPORTS = [
@@ -66,8 +68,8 @@ class Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("queries_per_item", ctypes.c_uint32), ("slab", ctypes.c_uint32),
                 ("bucket_order", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
-                ("tail_split", ctypes.c_uint32), ("bound", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("tail_split", ctypes.c_uint32), ("bound", ctypes.c_uint32), ("filter_unit", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 5)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -98,6 +100,8 @@ def options(**kw) -> Options:
             raise TypeError(f"unknown option {k!r}")
         if k == "bound":
             v = _code(BOUNDS, v)
+        if k == "filter_unit":
+            v = _code(UNITS, v)
         setattr(o, k, v)
     return o
 

@@ -1,0 +1,209 @@
+"""GPU parity of the matrix-core filter (FPM_UNIT_MATRIX): the filter test
+F_D <= t of Eq. 1 computed as an 8-bit integer contraction on the matrix
+cores.  Match sets equal the oracle's exact ones; survivor counts equal the
+oracle's count of pairs with F_D <= t (t = 2k; 4k for bigrams) and the
+vector-ALU path's, for occurrence, occurrence-halved and bigram
+fingerprints, Hamming and Levenshtein, k = 1..3, both schedules, tiles
+whose query and word counts are not multiples of the 64 x 64 pass, all
+pairs surviving, and the full-size workload in the benchmark's launch
+configuration."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_08475_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {"occ": oracle.OCC, "occh": oracle.OCCH, "qgram": oracle.QGRAM}
+NOMAP = np.full(256, oracle.NONE, dtype=np.uint8)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fpm(gpu):
+    from paper_1711_08475_amd import fpm as f
+
+    f.lib()
+    return f
+
+
+@pytest.fixture(scope="module")
+def small():
+    return datagen.workload("english_10k_q1k")
+
+
+_cache = {}
+
+
+def ref_match(key, d, q, metric, k):
+    if (key, metric, k) not in _cache:
+        _cache[(key, metric, k)] = oracle.match(d, q, metric, k)
+    return _cache[(key, metric, k)]
+
+
+def oracle_survivors(d, q, variant, mp, metric, k):
+    _, surv, _ = oracle.filter_stats(d, q, VARIANTS[variant], 16, NOMAP if variant == "qgram" else mp, metric, k)
+    return surv
+
+
+CASES = [
+    ("occ", oracle.HAM, 1), ("occ", oracle.LEV, 1), ("occ", oracle.LEV, 2), ("occ", oracle.LEV, 3),
+    ("occ", oracle.HAM, 3), ("occh", oracle.HAM, 1), ("occh", oracle.HAM, 2),
+    ("qgram", oracle.LEV, 1), ("qgram", oracle.HAM, 2), ("qgram", oracle.LEV, 3),
+]
+
+
+@pytest.mark.parametrize("variant,metric,k", CASES)
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_matrix_match_equals_oracle(fpm, small, variant, metric, k, schedule):
+    d, q = small
+    say("matrix", variant, metric, k, "schedule", schedule)
+    ix = fpm.fpm_build_fingerprints(d, variant, 16, "common")
+    got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule, filter_unit="matrix"), with_stats=True)
+    assert np.array_equal(got, ref_match("small", d, q, metric, k))
+    surv = oracle_survivors(d, q, variant, fpm.fpm_get_map(ix), metric, k)
+    assert st["survivors"] == surv
+    got_v, st_v = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule, filter_unit="valu"),
+                                with_stats=True)
+    assert np.array_equal(got_v, got)
+    assert (st_v["pairs_examined"], st_v["survivors"]) == (st["pairs_examined"], st["survivors"])
+
+
+@pytest.mark.parametrize("qt,slab,tail", [(16, 64, 0), (48, 128, 0), (64, 64, 0), (80, 192, 0), (112, 4096, 50),
+                                          (1024, 1 << 20, 0)])
+def test_matrix_ragged_tiles(fpm, small, qt, slab, tail):
+    """Tiles of 16..1024 queries and 64..1M words: passes with fewer than 64
+    queries (the lane halves see 0..32 of them) and fewer than 64 words."""
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    surv = oracle_survivors(d, q, "occ", fpm.fpm_get_map(ix), oracle.LEV, 1)
+    for sched in (0, 1):
+        say("matrix ragged", qt, slab, tail, sched)
+        got, st = fpm.fpm_match(ix, q, oracle.LEV, 1, fpm.options(schedule=sched, queries_per_item=qt, slab=slab,
+                                                                  tail_split=tail, filter_unit="matrix"),
+                                with_stats=True)
+        assert np.array_equal(got, ref_match("small", d, q, oracle.LEV, 1))
+        assert st["survivors"] == surv
+
+
+def test_matrix_every_pair_survives(fpm):
+    """No symbol in the map: every key is 0, F_D = 0 for every pair, so every
+    examined pair survives (the queue's overflow path: 2,048 survivors per
+    lane mask and pass)."""
+    rng = np.random.default_rng(12)
+    words = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(3001)]
+    queries = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(150)]
+    d, q = datagen.to_csr(words), datagen.to_csr(queries)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=NOMAP)
+    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
+        for qt, slab in [(64, 4096), (128, 64), (1024, 1 << 20)]:
+            say("matrix all survive", metric, k, qt, slab)
+            got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=qt, slab=slab,
+                                                                  filter_unit="matrix"), with_stats=True)
+            assert np.array_equal(got, oracle.match(d, q, metric, k))
+            assert st["survivors"] == st["pairs_examined"]
+
+
+def test_matrix_key_bits_one_at_a_time(fpm):
+    """Sixteen letters, each its own field: a query and a word that differ in
+    one symbol set differ in one or two key bits.  Every key position of the
+    contraction (both lane halves, both nibbles of each) decides some pair,
+    and the survivor count equals the oracle's."""
+    rng = np.random.default_rng(5)
+    letters = np.frombuffer(b"abcdefghijklmnop", np.uint8)
+    words = [bytes(rng.choice(letters, int(rng.integers(1, 12)))) for _ in range(4003)]
+    queries = []
+    for i in range(203):
+        w = bytearray(words[int(rng.integers(len(words)))])
+        if w and i % 3:
+            w[int(rng.integers(len(w)))] = int(rng.choice(letters))
+        queries.append(bytes(w))
+    d, q = datagen.to_csr(words), datagen.to_csr(queries)
+    mp = np.full(256, 255, dtype=np.uint8)
+    mp[letters] = np.arange(16)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=mp)
+    for metric, k in [(oracle.LEV, 1), (oracle.HAM, 1), (oracle.LEV, 2)]:
+        say("matrix sixteen letters", metric, k)
+        got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=64, slab=128,
+                                                              filter_unit="matrix"), with_stats=True)
+        assert np.array_equal(got, oracle.match(d, q, metric, k))
+        _, surv, _ = oracle.filter_stats(d, q, oracle.OCC, 16, mp, metric, k)
+        assert st["survivors"] == surv
+
+
+def test_matrix_filter_pairs_equal_valu(fpm, small):
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    say("matrix filter pairs")
+    pairs = fpm.fpm_filter_pairs(ix, q, "lev", 1)
+    fq = oracle.fingerprints(q, oracle.OCC, 16, fpm.fpm_get_map(ix))
+    fw = oracle.fingerprints(d, oracle.OCC, 16, fpm.fpm_get_map(ix))
+    assert np.all(oracle.fd(fq[pairs[:, 0]], fw[pairs[:, 1]], oracle.OCC, 16) <= 2)
+    assert pairs.shape[0] == oracle_survivors(d, q, "occ", fpm.fpm_get_map(ix), oracle.LEV, 1)
+
+
+def test_matrix_unit_errors(fpm, small):
+    d, q = small
+    say("matrix errors")
+    for variant, bits in [("occ", 32), ("count", 16), ("pos", 16), ("combo", 32)]:
+        ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
+        with pytest.raises(fpm.FpmError) as e:
+            fpm.fpm_match(ix, q, "ham", 1, fpm.options(filter_unit="matrix"))
+        assert e.value.status == fpm.FPM_EUNSUPPORTED
+        # auto falls back to the vector ALUs
+        assert np.array_equal(fpm.fpm_match(ix, q, "ham", 1), ref_match("small", d, q, oracle.HAM, 1))
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, q, "lev", 1, fpm.options(filter_unit="matrix", bound="asym"))
+    assert e.value.status == fpm.FPM_EUNSUPPORTED
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match(ix, q, "lev", 1, fpm.options(filter_unit=3))
+    assert e.value.status == fpm.FPM_EINVAL
+    # empty query list, a single empty query, one word
+    assert fpm.fpm_match(ix, datagen.to_csr([]), "lev", 1, fpm.options(filter_unit="matrix")).shape[0] == 0
+    one = datagen.to_csr([b""])
+    assert np.array_equal(fpm.fpm_match(ix, one, "lev", 1, fpm.options(filter_unit="matrix")),
+                          oracle.match(d, one, oracle.LEV, 1))
+    ix1 = fpm.fpm_build_fingerprints(datagen.to_csr([b"abc"]), "occ", 16, "common")
+    qs = datagen.to_csr([b"abc", b"abd", b"ab", b"abcd", b"xyz", b"ab", b"bca"])
+    assert np.array_equal(fpm.fpm_match(ix1, qs, "lev", 1, fpm.options(filter_unit="matrix")),
+                          oracle.match(datagen.to_csr([b"abc"]), qs, oracle.LEV, 1))
+
+
+def test_matrix_full_size_sampled_parity(fpm):
+    """english_1m_q10k with the learned grouping (occ16, Lev k = 1) in the
+    benchmark's launch configuration (batched, persistent, hipGraph, tuned
+    tiles): the matrix and vector paths return the same match list and
+    survivor count, and sampled query rows equal the oracle's."""
+    import torch
+
+    from paper_1711_08475_amd import learn
+
+    d, q = datagen.workload("english_1m_q10k")
+    nq = q[1].size - 1
+    mp, _ = learn.load_map("english_1m_q10k_occ16_k1")
+    say("matrix full size")
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=mp)
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()
+    res = {}
+    for unit in ("matrix", "valu"):
+        plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), oracle.LEV, 1,
+                                   fpm.options(schedule=1, queries_per_item=128, slab=1024, bucket_order=1,
+                                               filter_unit=unit))
+        fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+        res[unit] = (fpm.fpm_plan_copy_matches(plan), fpm.fpm_plan_result(plan)[2])
+        del plan
+    assert np.array_equal(res["matrix"][0], res["valu"][0])
+    assert res["matrix"][1]["survivors"] == res["valu"][1]["survivors"]
+    sample = np.random.default_rng(17).choice(nq, 48, replace=False)
+    sample.sort()
+    ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, 1, length_pruned=True)
+    ref[:, 0] = sample[ref[:, 0]]
+    got = res["matrix"][0]
+    assert np.array_equal(got[np.isin(got[:, 0], sample)], ref)

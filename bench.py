@@ -58,7 +58,14 @@ WORKLOAD_TEXT = {
 def metric_name(metric: str, k: int) -> str:
     return f"{'Lev' if metric == 'lev' else 'Ham'} k={k} query-word pairs/sec (1 MI355X), learned+batched vs plain filter"
 PEAK_INT_OPS = 256 * 64 * 2.4e9  # CUs x lanes x clock: one 32-bit VALU op per lane per clock
-# VALU instructions per examined pair in the filter loop (see fpm_match.hip)
+PEAK_INT8_MATRIX_OPS = 5.0e15  # MI355X dense int8 matrix-core peak (ops/s)
+# matrix-core filter: per pair the vector ALUs shift one sign bit into a
+# survivor mask, and the matrix cores run a 32-deep int8 contraction
+# (v_mfma_i32_32x32x32_i8: 2 x 32 ops per output)
+MATRIX_VALU_OPS_PER_PAIR = 1
+MATRIX_INT8_OPS_PER_PAIR = 64
+FPM_UNIT_MATRIX = 2
+# VALU instructions per examined pair in the vector filter loop (see fpm_match.hip)
 FILTER_OPS = {("occ", 16): 3, ("occ", 32): 3, ("occh", 16): 3, ("occh", 32): 3, ("count", 16): 3, ("count", 32): 5,
               ("pos", 16): 8, ("pos", 32): 8, ("qgram", 16): 3, ("qgram", 32): 3,
               ("combo", 16): 6, ("combo", 32): 6}
@@ -317,7 +324,9 @@ def main():
     head = names[-1]
     r = results[head]
     st = r["stats"]
-    ops = FILTER_OPS[(args.variant, args.bits)] * st["pairs_examined"] + st["verify_cells"]
+    matrix = st.get("filter_unit") == FPM_UNIT_MATRIX
+    per_pair = MATRIX_VALU_OPS_PER_PAIR if matrix else FILTER_OPS[(args.variant, args.bits)]
+    ops = per_pair * st["pairs_examined"] + st["verify_cells"]
     achieved = ops / (r["kernel_ms"] * 1e-3) if r["kernel_ms"] else None
     traffic = load_traffic(head, args.workload)
     roofline = {
@@ -328,9 +337,16 @@ def main():
         "frac": achieved / PEAK_INT_OPS if achieved else None,
         "traffic": traffic["bytes_per_launch"] if traffic else None,
         "kernel": "k_match (fused filter + LDS queue + verify)",
+        "filter_unit": "matrix" if matrix else "valu",
+        "valu_ops_per_pair": per_pair,
         "ops_per_launch": ops,
         "kernel_ms": r["kernel_ms"],
     }
+    if matrix and r["kernel_ms"]:
+        m_ops = MATRIX_INT8_OPS_PER_PAIR * st["pairs_examined"]
+        roofline["matrix_cores"] = {"achieved": m_ops / (r["kernel_ms"] * 1e-3) / 1e12,
+                                    "peak": PEAK_INT8_MATRIX_OPS / 1e12, "unit": "int8 Tops/s",
+                                    "frac": m_ops / (r["kernel_ms"] * 1e-3) / PEAK_INT8_MATRIX_OPS}
 
     cpu = None
     sampled_parity = None

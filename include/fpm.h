@@ -143,6 +143,8 @@ typedef struct {
     uint64_t verify_cells;   /* sum over survivors of (2k+1) * min(m, n) */
     float ms;                /* device time of the match pipeline (hip events) */
     uint32_t work_items;     /* work items the schedule processed */
+    uint32_t filter_unit;    /* fpm_filter_unit that ran the filter test: FPM_UNIT_VALU or FPM_UNIT_MATRIX
+                                (FPM_UNIT_AUTO for FPM_SCHED_BRUTE, which has no filter) */
 } fpm_stats;
 
 /* Tuning options; zero fields take defaults.  The match result never

@@ -940,6 +940,7 @@ fpm_status fpm_plan_result(fpm_plan *p, const fpm_hit **d_matches, uint64_t *n_o
     st.verify_cells = c.cells;
     st.ms = ms;
     st.work_items = c.n_items;
+    st.filter_unit = p->kind == kAll ? FPM_UNIT_AUTO : p->mx_width ? FPM_UNIT_MATRIX : FPM_UNIT_VALU;
     if (d_matches)
         *d_matches = (const fpm_hit *)p->triples;
     if (n_out)

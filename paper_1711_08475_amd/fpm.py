@@ -58,7 +58,7 @@ class Hit(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("pairs_logical", ctypes.c_uint64), ("pairs_examined", ctypes.c_uint64),
                 ("survivors", ctypes.c_uint64), ("matches", ctypes.c_uint64), ("verify_cells", ctypes.c_uint64),
-                ("ms", ctypes.c_float), ("work_items", ctypes.c_uint32)]
+                ("ms", ctypes.c_float), ("work_items", ctypes.c_uint32), ("filter_unit", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

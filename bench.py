@@ -217,7 +217,8 @@ def main():
                          "host every step and always runs one")
     ap.add_argument("--filter-unit", default="auto", choices=["auto", "valu", "matrix"],
                     help="where the filter test runs: auto (matrix cores for 16-bit occurrence, "
-                         "occurrence-halved and bigram keys under the paper's rule, else vector ALUs), valu, matrix")
+                         "occurrence-halved and bigram keys under the paper's rule, else vector ALUs), valu, "
+                         "matrix (also 32-bit and 16-bit count keys)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()

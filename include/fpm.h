@@ -108,23 +108,26 @@ typedef enum { FPM_SCHED_PLAIN = 0, FPM_SCHED_BATCHED = 1, FPM_SCHED_BRUTE = 2 }
 typedef enum { FPM_BOUND_FD = 0, FPM_BOUND_ASYM = 1 } fpm_bound;
 
 /* Where the filter test F_D <= t (Eq. 1; t = 2k, bigrams 4k) runs.
- *   FPM_UNIT_AUTO (default): on the matrix cores where the key family
- *     allows it, else on the vector ALUs.
+ *   FPM_UNIT_AUTO (default): on the matrix cores for 16-bit occurrence,
+ *     occurrence-halved and bigram keys under the paper's rule (where they
+ *     are faster), else on the vector ALUs.
  *   FPM_UNIT_VALU: vector ALUs only -- per pair one XOR, one popcount and
  *     one shift of the result's sign bit into a survivor mask.
  *   FPM_UNIT_MATRIX: matrix cores; FPM_EUNSUPPORTED where the key family
  *     does not allow it.  F_D of two bit vectors is an inner product: with
  *     every key bit written as a signed byte (+1 for 0, -1 for 1 on the
  *     query side, the negation on the word side), the product of a query
- *     row and a word column over the W key positions is 2 F_D - W.  One
- *     8-bit integer matrix instruction (32 x 32 outputs, K = W = 16 or 32)
- *     adds W - 2t - 1 and yields 2 F_D - 2t - 1 for 1,024 pairs, negative
- *     exactly when the pair survives; the sign bits go into the same
- *     survivor masks as on the vector path.  Offered for the paper's rule
- *     (FPM_BOUND_FD) on keys of up to 32 bits whose F_D is the popcount of
- *     their XOR: occurrence, occurrence-halved and 16-bit count
- *     fingerprints, and bigrams.  Survivors and matches are the same on
- *     both units. */
+ *     row and a word column over 16 key positions is 2 F_D - 16.  One
+ *     8-bit integer matrix instruction (32 x 32 outputs, 32 contraction
+ *     positions) takes 16 key bits and, in a spare position, the threshold
+ *     term, and yields 2 F_D - 2t - 1 for 1,024 pairs, negative exactly
+ *     when the pair survives (32-bit keys: two instructions per tile, the
+ *     second accumulating bits 16..31 onto the first); the sign bits go
+ *     into the same survivor masks as on the vector path.  Offered for the
+ *     paper's rule (FPM_BOUND_FD) on keys whose F_D is the popcount of
+ *     their XOR: occurrence and occurrence-halved fingerprints (16 and 32
+ *     bits), 16-bit count fingerprints (24-bit thermometer keys) and
+ *     bigrams.  Survivors and matches are the same on both units. */
 typedef enum { FPM_UNIT_AUTO = 0, FPM_UNIT_VALU = 1, FPM_UNIT_MATRIX = 2 } fpm_filter_unit;
 
 /* One reported match.  `query` and `word` index the caller's lists. */

@@ -642,16 +642,21 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
                                       "fingerprints only");
     }
     p->kind = p->opt.schedule == FPM_SCHED_BRUTE ? kAll : p->asym ? ix->kind_asym : ix->kind;
-    // the matrix-core filter: the paper's rule on 16-bit keys whose F_D is
-    // the popcount of their XOR
-    const bool mx_ok = !p->asym && (p->kind == kPop32 || p->kind == kQgram32) && ix->bits == 16 &&
-                       ix->variant != FPM_COUNT;
+    // the matrix-core filter: the paper's rule on keys of up to 32 bits whose
+    // F_D is the popcount of their XOR (16-bit count keys are 24-bit
+    // thermometer codes: 32-bit tiles)
+    const bool mx_ok = !p->asym && (p->kind == kPop32 || p->kind == kQgram32);
     if (p->opt.filter_unit == FPM_UNIT_MATRIX && !mx_ok) {
         delete p;
-        return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on 16-bit occurrence, "
-                                      "occurrence-halved and bigram fingerprints");
+        return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on occurrence, "
+                                      "occurrence-halved, 16-bit count and bigram fingerprints");
     }
-    p->mx_width = mx_ok && p->opt.filter_unit != FPM_UNIT_VALU ? 16 : 0;
+    // auto: matrix cores for 16-bit keys only (32-bit tiles carry half the
+    // pairs per pass and four times the query-row loads per pair; measured
+    // slower than the vector filter on every 32-bit workload)
+    const int key_width = ix->bits == 16 && ix->variant != FPM_COUNT ? 16 : 32;
+    const bool want = p->opt.filter_unit == FPM_UNIT_MATRIX || (p->opt.filter_unit == FPM_UNIT_AUTO && key_width == 16);
+    p->mx_width = mx_ok && want ? key_width : 0;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;
@@ -667,7 +672,7 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         return hip_fail(e, "fpm_plan_create alloc");
     }
     if (p->mx_width) {
-        const size_t qb = ((size_t)max_queries + 64) * kMxRowBytes;
+        const size_t qb = ((size_t)max_queries + 64) * kMxRowBytes * (p->mx_width / 16);
         if ((e = dalloc(&p->qexp, qb)) || (e = hipMemset(p->qexp, 0, qb))) {
             plan_free(p);
             return hip_fail(e, "fpm_plan_create alloc");

@@ -190,16 +190,16 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
 //   persistent: grid = persistent_blocks; wave w takes item w first, then
 //   items from the striped counters;
 //   otherwise grid covers host_items items, one per wave.
-//   key_width 16: the filter test runs on the matrix cores over 16-bit keys
-//   (key kinds kPop32 and kQgram32 only; a.qexp filled by
-//   launch_expand_keys); 0: on the vector ALUs.
+//   key_width 16 or 32: the filter test runs on the matrix cores over keys
+//   of that many bits (key kinds kPop32 and kQgram32 only; a.qexp filled
+//   by launch_expand_keys); 0: on the vector ALUs.
 hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s);
 
-// Query side of the matrix-core filter: each of the n 16-bit keys becomes a
+// Query side of the matrix-core filter: each of the n keys becomes a
 // kMxRowBytes-byte row of signed bytes (+1 for a clear bit, -1 for a set
-// bit) with the threshold byte 2t - 15 (t: the family's F_D threshold,
-// at most 15); width must be 16.
+// bit) per 16 key bits (width 16: one row, 32: two), the first with the
+// threshold byte 2t + 1 - width (t: the family's F_D threshold, at most 15).
 constexpr int kMxRowBytes = 32;
 void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s);
 

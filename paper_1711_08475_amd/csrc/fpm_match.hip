@@ -725,14 +725,28 @@ __device__ __forceinline__ v4i_t word_fragment(WordBytes b)
     return f;
 }
 
-// One 32 x 32 tile: shift the 16 sign bits of the lane's results into m,
-// register 15 first.
-__device__ __forceinline__ void mx_tile(v4i_t qa, v4i_t wb, uint32_t &m)
+// Shift the 16 sign bits of a tile's results into m, register 15 first.
+__device__ __forceinline__ void sign_bits(const v16i_t &d, uint32_t &m)
 {
-    const v16i_t d = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa, wb, (v16i_t)(0), 0, 0, 0);
 #pragma unroll
     for (int r = 15; r >= 0; --r)
         m = __builtin_amdgcn_alignbit(m, (uint32_t)d[r], 31);
+}
+
+// One 32 x 32 tile of 16-bit keys.
+__device__ __forceinline__ void mx_tile(v4i_t qa, v4i_t wb, uint32_t &m)
+{
+    sign_bits(__builtin_amdgcn_mfma_i32_32x32x32_i8(qa, wb, (v16i_t)(0), 0, 0, 0), m);
+}
+
+// One 32 x 32 tile of 32-bit keys: bits 0 .. 15 with the threshold position
+// (2t - 31 on the query side), then bits 16 .. 31 in the same layout with
+// no threshold, accumulated onto the first product: (2 F_D0 - 16 + 31 - 2t)
+// + (2 F_D1 - 16) = 2 F_D - 2t - 1.
+__device__ __forceinline__ void mx_tile2(v4i_t qa0, v4i_t qa1, v4i_t wb0, v4i_t wb1, uint32_t &m)
+{
+    const v16i_t d = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa0, wb0, (v16i_t)(0), 0, 0, 0);
+    sign_bits(__builtin_amdgcn_mfma_i32_32x32x32_i8(qa1, wb1, d, 0, 0, 0), m);
 }
 
 // ------------------------------------------------------------ schedule
@@ -787,7 +801,7 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, u
     return n_items;
 }
 
-template <int KIND, int METRIC, int K, bool PERSISTENT, bool MX>
+template <int KIND, int METRIC, int K, bool PERSISTENT, int MX>
 __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 {
     using F = Filter<KIND>;
@@ -828,7 +842,7 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                 it.de = it.ds;
         }
         uint32_t qlen = 0;
-        if constexpr (MX) {
+        if constexpr (MX == 16) {
             // matrix cores: 64 queries x 64 words per pass, the lane's words
             // e0 + lane % 32 and e0 + 32 + lane % 32, queries 32 (lane / 32) + b
             const uint32_t h = lane >> 5, col = lane & 31u;
@@ -862,6 +876,41 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                     append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, survivors, cells, out,
                                       ocount);
                     append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, survivors, cells,
+                                      out, ocount);
+                    while (qlen >= 64)
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                }
+            }
+        } else if constexpr (MX == 32) {
+            // matrix cores, 32-bit keys: 64 queries x 32 words per pass (two
+            // chained products per tile), the lane's word e0 + lane % 32,
+            // queries 32 (lane / 32) + b; query rows of 2 x kMxRowBytes
+            const uint32_t h = lane >> 5, col = lane & 31u;
+            const uint32_t qrow = 32u * ((col >> 2) & 1u) + 4u * (col >> 3) + (col & 3u);
+            const uint32_t qoff = qrow * (2u * kMxRowBytes) + 16u * h;
+            uint32_t w_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
+            for (uint32_t e0 = it.ds; e0 < it.de; e0 += 32) {
+                const WordBytes x0 = word_bytes(w_next, h), x1 = word_bytes(w_next >> 16, h);
+                w_next = (e0 + 32 + col < it.de) ? dkeys[e0 + 32 + col] : 0u;
+                for (uint32_t j0 = 0; j0 < it.qn; j0 += 64) {
+                    const v4i_t b0 = word_fragment(x0), b1 = word_fragment(x1);
+                    // rows qs + j0 + 63 at most: the expanded rows carry 64 padding rows
+                    const uint8_t *qb = a.qexp + (size_t)(it.qs + j0) * (2u * kMxRowBytes) + qoff;
+                    const v4i_t q00 = *(const v4i_t *)(qb);
+                    const v4i_t q01 = *(const v4i_t *)(qb + kMxRowBytes);
+                    const v4i_t q10 = *(const v4i_t *)(qb + 16u * 2u * kMxRowBytes);
+                    const v4i_t q11 = *(const v4i_t *)(qb + 16u * 2u * kMxRowBytes + kMxRowBytes);
+                    uint32_t m = 0;
+                    mx_tile2(q10, q11, b0, b1, m);
+                    mx_tile2(q00, q01, b0, b1, m);
+                    const uint32_t nqc = min(64u, it.qn - j0);
+                    if (nqc < 64u || e0 + 32 > it.de) {
+                        const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
+                        const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
+                        m = (e0 + col < it.de) ? m & qm : 0u;
+                    }
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, m,
+                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, survivors, cells,
                                       out, ocount);
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
@@ -1099,7 +1148,7 @@ __global__ void k_verify_pairs(StrSetView q, const uint32_t *qinv, StrSetView d,
     dist[i] = verify<METRIC, K>(q.str + q.soff[qi], q.len[qi], d.str + d.soff[wi], d.len[wi]);
 }
 
-template <int KIND, int METRIC, int K, bool MX = false>
+template <int KIND, int METRIC, int K, int MX = 0>
 hipError_t launch_kmk(const MatchArgs &a, bool persistent, uint32_t pblocks, uint32_t host_items, hipStream_t s)
 {
     if (persistent) {
@@ -1113,7 +1162,7 @@ hipError_t launch_kmk(const MatchArgs &a, bool persistent, uint32_t pblocks, uin
     return hipGetLastError();
 }
 
-template <int KIND, bool MX = false>
+template <int KIND, int MX = 0>
 hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persistent, uint32_t pblocks,
                        uint32_t host_items, hipStream_t s)
 {
@@ -1134,24 +1183,31 @@ hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persiste
 // Query rows of the matrix filter: key bits 0 .. 7 as bytes 0 .. 7, the
 // threshold byte 2t - 15 at 8, bits 8 .. 15 as bytes 16 .. 23, zeros
 // elsewhere (1 - 2 q_j: 0x01 for a clear bit, 0xFF for a set bit).
-__global__ void k_expand_keys(const uint32_t *keys, uint32_t n, uint32_t t, uint8_t *out)
+// 32-bit keys: two such rows per query, the second for bits 16 .. 31
+// with a zero threshold byte; the threshold byte of the first is then
+// 2t - 31, because the second part's product adds its own -16 (in general
+// 2t + 1 - 16 * parts).
+__global__ void k_expand_keys(const uint32_t *keys, uint32_t n, uint32_t t, uint32_t parts, uint8_t *out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const uint32_t w = keys[i];
-    uint4 lo, hi;
-    lo.x = nibble_bytes(w & 15u, 0xFFFFFFFFu, 0x01010101u);
-    lo.y = nibble_bytes((w >> 4) & 15u, 0xFFFFFFFFu, 0x01010101u);
-    lo.z = (2u * t - 15u) & 0xFFu;
-    lo.w = 0u;
-    hi.x = nibble_bytes((w >> 8) & 15u, 0xFFFFFFFFu, 0x01010101u);
-    hi.y = nibble_bytes((w >> 12) & 15u, 0xFFFFFFFFu, 0x01010101u);
-    hi.z = 0u;
-    hi.w = 0u;
-    uint4 *row = (uint4 *)(out + (size_t)i * kMxRowBytes);
-    row[0] = lo;
-    row[1] = hi;
+    const uint32_t key = keys[i];
+    for (uint32_t p = 0; p < parts; ++p) {
+        const uint32_t w = key >> (16u * p);
+        uint4 lo, hi;
+        lo.x = nibble_bytes(w & 15u, 0xFFFFFFFFu, 0x01010101u);
+        lo.y = nibble_bytes((w >> 4) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        lo.z = p == 0 ? (2u * t + 1u - 16u * parts) & 0xFFu : 0u;
+        lo.w = 0u;
+        hi.x = nibble_bytes((w >> 8) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        hi.y = nibble_bytes((w >> 12) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        hi.z = 0u;
+        hi.w = 0u;
+        uint4 *row = (uint4 *)(out + ((size_t)i * parts + p) * kMxRowBytes);
+        row[0] = lo;
+        row[1] = hi;
+    }
 }
 
 }  // namespace
@@ -1192,22 +1248,23 @@ void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uin
 
 void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s)
 {
-    (void)width;  // 16-bit keys: one row layout
     if (n)
-        hipLaunchKernelGGL(k_expand_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, t, out);
+        hipLaunchKernelGGL(k_expand_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, t,
+                           width == 32 ? 2u : 1u, out);
 }
 
 hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s)
 {
     if (key_width) {
-        if (key_width != 16)
+        if ((key_width != 16 && key_width != 32) || (key_kind != kPop32 && key_kind != kQgram32))
             return hipErrorInvalidValue;
-        if (key_kind == kPop32)
-            return launch_kind<kPop32, true>(a, metric, k, persistent, persistent_blocks, host_items, s);
-        if (key_kind == kQgram32)
-            return launch_kind<kQgram32, true>(a, metric, k, persistent, persistent_blocks, host_items, s);
-        return hipErrorInvalidValue;
+        if (key_width == 16)
+            return key_kind == kPop32
+                       ? launch_kind<kPop32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                       : launch_kind<kQgram32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        return key_kind == kPop32 ? launch_kind<kPop32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                                  : launch_kind<kQgram32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
     }
     switch (key_kind) {
     case kPop32:

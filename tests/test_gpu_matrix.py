@@ -2,11 +2,11 @@
 F_D <= t of Eq. 1 computed as an 8-bit integer contraction on the matrix
 cores.  Match sets equal the oracle's exact ones; survivor counts equal the
 oracle's count of pairs with F_D <= t (t = 2k; 4k for bigrams) and the
-vector-ALU path's, for occurrence, occurrence-halved and bigram
-fingerprints, Hamming and Levenshtein, k = 1..3, both schedules, tiles
-whose query and word counts are not multiples of the 64 x 64 pass, all
-pairs surviving, and the full-size workload in the benchmark's launch
-configuration."""
+vector-ALU path's, for occurrence, occurrence-halved, 16-bit count and
+bigram fingerprints (16- and 32-bit keys), Hamming and Levenshtein,
+k = 1..3, both schedules, tiles whose query and word counts are not
+multiples of the pass, all pairs surviving, and full-size workloads in the
+benchmark's launch configuration."""
 import numpy as np
 import pytest
 
@@ -15,7 +15,7 @@ from paper_1711_08475_amd import datagen
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = {"occ": oracle.OCC, "occh": oracle.OCCH, "qgram": oracle.QGRAM}
+VARIANTS = {"occ": oracle.OCC, "occh": oracle.OCCH, "qgram": oracle.QGRAM, "count": oracle.COUNT}
 NOMAP = np.full(256, oracle.NONE, dtype=np.uint8)
 
 
@@ -45,44 +45,51 @@ def ref_match(key, d, q, metric, k):
     return _cache[(key, metric, k)]
 
 
-def oracle_survivors(d, q, variant, mp, metric, k):
-    _, surv, _ = oracle.filter_stats(d, q, VARIANTS[variant], 16, NOMAP if variant == "qgram" else mp, metric, k)
+def oracle_survivors(d, q, variant, mp, metric, k, bits=16):
+    _, surv, _ = oracle.filter_stats(d, q, VARIANTS[variant], bits, NOMAP if variant == "qgram" else mp, metric, k)
     return surv
 
 
 CASES = [
-    ("occ", oracle.HAM, 1), ("occ", oracle.LEV, 1), ("occ", oracle.LEV, 2), ("occ", oracle.LEV, 3),
-    ("occ", oracle.HAM, 3), ("occh", oracle.HAM, 1), ("occh", oracle.HAM, 2),
-    ("qgram", oracle.LEV, 1), ("qgram", oracle.HAM, 2), ("qgram", oracle.LEV, 3),
+    ("occ", 16, oracle.HAM, 1), ("occ", 16, oracle.LEV, 1), ("occ", 16, oracle.LEV, 2), ("occ", 16, oracle.LEV, 3),
+    ("occ", 16, oracle.HAM, 3), ("occh", 16, oracle.HAM, 1), ("occh", 16, oracle.HAM, 2),
+    ("qgram", 16, oracle.LEV, 1), ("qgram", 16, oracle.HAM, 2), ("qgram", 16, oracle.LEV, 3),
+    ("occ", 32, oracle.LEV, 1), ("occ", 32, oracle.HAM, 1), ("occ", 32, oracle.LEV, 2), ("occ", 32, oracle.LEV, 3),
+    ("occh", 32, oracle.HAM, 2), ("count", 16, oracle.LEV, 1), ("count", 16, oracle.HAM, 2),
+    ("qgram", 32, oracle.LEV, 1), ("qgram", 32, oracle.LEV, 2),
 ]
 
 
-@pytest.mark.parametrize("variant,metric,k", CASES)
+@pytest.mark.parametrize("variant,bits,metric,k", CASES)
 @pytest.mark.parametrize("schedule", [0, 1])
-def test_matrix_match_equals_oracle(fpm, small, variant, metric, k, schedule):
+def test_matrix_match_equals_oracle(fpm, small, variant, bits, metric, k, schedule):
     d, q = small
-    say("matrix", variant, metric, k, "schedule", schedule)
-    ix = fpm.fpm_build_fingerprints(d, variant, 16, "common")
+    say("matrix", variant, bits, metric, k, "schedule", schedule)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
     got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule, filter_unit="matrix"), with_stats=True)
+    assert st["filter_unit"] == fpm.FPM_UNIT_MATRIX
     assert np.array_equal(got, ref_match("small", d, q, metric, k))
-    surv = oracle_survivors(d, q, variant, fpm.fpm_get_map(ix), metric, k)
+    surv = oracle_survivors(d, q, variant, fpm.fpm_get_map(ix), metric, k, bits)
     assert st["survivors"] == surv
     got_v, st_v = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=schedule, filter_unit="valu"),
                                 with_stats=True)
+    assert st_v["filter_unit"] == fpm.FPM_UNIT_VALU
     assert np.array_equal(got_v, got)
     assert (st_v["pairs_examined"], st_v["survivors"]) == (st["pairs_examined"], st["survivors"])
 
 
 @pytest.mark.parametrize("qt,slab,tail", [(16, 64, 0), (48, 128, 0), (64, 64, 0), (80, 192, 0), (112, 4096, 50),
                                           (1024, 1 << 20, 0)])
-def test_matrix_ragged_tiles(fpm, small, qt, slab, tail):
+@pytest.mark.parametrize("bits", [16, 32])
+def test_matrix_ragged_tiles(fpm, small, qt, slab, tail, bits):
     """Tiles of 16..1024 queries and 64..1M words: passes with fewer than 64
-    queries (the lane halves see 0..32 of them) and fewer than 64 words."""
+    queries (the lane halves see 0..32 of them) and fewer than 64 (16-bit
+    keys) or 32 (32-bit keys) words."""
     d, q = small
-    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
-    surv = oracle_survivors(d, q, "occ", fpm.fpm_get_map(ix), oracle.LEV, 1)
+    ix = fpm.fpm_build_fingerprints(d, "occ", bits, "common")
+    surv = oracle_survivors(d, q, "occ", fpm.fpm_get_map(ix), oracle.LEV, 1, bits)
     for sched in (0, 1):
-        say("matrix ragged", qt, slab, tail, sched)
+        say("matrix ragged", bits, qt, slab, tail, sched)
         got, st = fpm.fpm_match(ix, q, oracle.LEV, 1, fpm.options(schedule=sched, queries_per_item=qt, slab=slab,
                                                                   tail_split=tail, filter_unit="matrix"),
                                 with_stats=True)
@@ -98,14 +105,15 @@ def test_matrix_every_pair_survives(fpm):
     words = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(3001)]
     queries = [bytes(rng.integers(97, 100, size=int(rng.integers(1, 7)))) for _ in range(150)]
     d, q = datagen.to_csr(words), datagen.to_csr(queries)
-    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=NOMAP)
-    for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
-        for qt, slab in [(64, 4096), (128, 64), (1024, 1 << 20)]:
-            say("matrix all survive", metric, k, qt, slab)
-            got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=qt, slab=slab,
-                                                                  filter_unit="matrix"), with_stats=True)
-            assert np.array_equal(got, oracle.match(d, q, metric, k))
-            assert st["survivors"] == st["pairs_examined"]
+    for bits in (16, 32):
+        ix = fpm.fpm_build_fingerprints(d, "occ", bits, custom_map=NOMAP)
+        for metric, k in [(oracle.LEV, 1), (oracle.LEV, 2), (oracle.HAM, 1)]:
+            for qt, slab in [(64, 4096), (128, 64), (1024, 1 << 20)]:
+                say("matrix all survive", bits, metric, k, qt, slab)
+                got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=qt, slab=slab,
+                                                                      filter_unit="matrix"), with_stats=True)
+                assert np.array_equal(got, oracle.match(d, q, metric, k))
+                assert st["survivors"] == st["pairs_examined"]
 
 
 def test_matrix_key_bits_one_at_a_time(fpm):
@@ -149,7 +157,7 @@ def test_matrix_filter_pairs_equal_valu(fpm, small):
 def test_matrix_unit_errors(fpm, small):
     d, q = small
     say("matrix errors")
-    for variant, bits in [("occ", 32), ("count", 16), ("pos", 16), ("combo", 32)]:
+    for variant, bits in [("count", 32), ("pos", 16), ("pos", 32), ("combo", 32)]:
         ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
         with pytest.raises(fpm.FpmError) as e:
             fpm.fpm_match(ix, q, "ham", 1, fpm.options(filter_unit="matrix"))
@@ -204,6 +212,65 @@ def test_matrix_full_size_sampled_parity(fpm):
     sample = np.random.default_rng(17).choice(nq, 48, replace=False)
     sample.sort()
     ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, 1, length_pruned=True)
+    ref[:, 0] = sample[ref[:, 0]]
+    got = res["matrix"][0]
+    assert np.array_equal(got[np.isin(got[:, 0], sample)], ref)
+
+
+def test_matrix_thirty_two_letters(fpm):
+    """Thirty-two letters, each its own field of a 32-bit key: pairs that
+    differ in one symbol exercise every key position of both chained
+    products (bits 0..15 with the threshold, bits 16..31)."""
+    rng = np.random.default_rng(8)
+    letters = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz012345", np.uint8)
+    words = [bytes(rng.choice(letters, int(rng.integers(1, 12)))) for _ in range(4007)]
+    queries = []
+    for i in range(211):
+        w = bytearray(words[int(rng.integers(len(words)))])
+        if w and i % 3:
+            w[int(rng.integers(len(w)))] = int(rng.choice(letters))
+        queries.append(bytes(w))
+    d, q = datagen.to_csr(words), datagen.to_csr(queries)
+    mp = np.full(256, 255, dtype=np.uint8)
+    mp[letters] = np.arange(32)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 32, custom_map=mp)
+    for metric, k in [(oracle.LEV, 1), (oracle.HAM, 1), (oracle.LEV, 2)]:
+        say("matrix thirty-two letters", metric, k)
+        got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=64, slab=128,
+                                                              filter_unit="matrix"), with_stats=True)
+        assert np.array_equal(got, oracle.match(d, q, metric, k))
+        _, surv, _ = oracle.filter_stats(d, q, oracle.OCC, 32, mp, metric, k)
+        assert st["survivors"] == surv
+
+
+def test_matrix_url_full_size_sampled_parity(fpm):
+    """url_1m_q10k with its learned grouping (occ32, Lev k = 2) in the
+    batched launch configuration: matrix and vector paths agree on the match
+    list and survivor count, and sampled query rows equal the oracle's."""
+    import torch
+
+    from paper_1711_08475_amd import learn
+
+    d, q = datagen.workload("url_1m_q10k")
+    nq = q[1].size - 1
+    mp, _ = learn.load_map("url_1m_q10k_occ32_k2")
+    say("matrix url full size")
+    ix = fpm.fpm_build_fingerprints(d, "occ", 32, custom_map=mp)
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()
+    res = {}
+    for unit in ("matrix", "valu"):
+        plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), oracle.LEV, 2,
+                                   fpm.options(schedule=1, queries_per_item=128, slab=1024, filter_unit=unit))
+        fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+        res[unit] = (fpm.fpm_plan_copy_matches(plan), fpm.fpm_plan_result(plan)[2])
+        del plan
+    assert np.array_equal(res["matrix"][0], res["valu"][0])
+    assert res["matrix"][1]["survivors"] == res["valu"][1]["survivors"]
+    sample = np.random.default_rng(19).choice(nq, 24, replace=False)
+    sample.sort()
+    ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, 2, length_pruned=True)
     ref[:, 0] = sample[ref[:, 0]]
     got = res["matrix"][0]
     assert np.array_equal(got[np.isin(got[:, 0], sample)], ref)

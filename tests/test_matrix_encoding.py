@@ -32,11 +32,11 @@ def signed(b):
     return np.frombuffer(bytes(b), dtype=np.int8).astype(np.int64)
 
 
-def query_row(key, t):
+def query_row(key, t, threshold_byte=None):
     row = bytearray(32)
     for d, nib_shift in ((0, 0), (4, 4), (16, 8), (20, 12)):
         row[d:d + 4] = perm_bytes(0xFFFFFFFF, 0x01010101, nibble_sel((key >> nib_shift) & 15))
-    row[8] = (2 * t - 15) & 0xFF
+    row[8] = (2 * t - 15 if threshold_byte is None else threshold_byte) & 0xFF
     return signed(row)
 
 
@@ -106,3 +106,23 @@ def test_tile_layout_and_row_permutation():
             q = 32 * h + b
             want = bin(int(qkeys[q]) ^ int(wkeys[j])).count("1") <= t
             assert ((int(masks[lane]) >> b) & 1) == int(want)
+
+
+@pytest.mark.parametrize("t", [2, 4, 6, 12])
+def test_two_part_product_for_32_bit_keys(t):
+    """32-bit keys: bits 0..15 with the threshold byte 2t - 31, then bits
+    16..31 with a zero threshold byte, the second product accumulated onto
+    the first: (2 F_D0 - 16 + 31 - 2t) + (2 F_D1 - 16) = 2 F_D - 2t - 1."""
+    rng = np.random.default_rng(40 + t)
+    qs = rng.integers(0, 1 << 32, 200, dtype=np.uint64)
+    ws = rng.integers(0, 1 << 32, 200, dtype=np.uint64)
+    ws[:100] = qs[:100] ^ (np.uint64(1) << rng.integers(0, 32, 100).astype(np.uint64))
+    A0 = np.stack([query_row(int(q) & 0xFFFF, t, 2 * t - 31) for q in qs])
+    A1 = np.stack([query_row(int(q) >> 16, t, 0) for q in qs])
+    B0 = np.stack([word_column(int(w) & 0xFFFF) for w in ws])
+    B1 = np.stack([word_column(int(w) >> 16) for w in ws])
+    prod = A0 @ B0.T + A1 @ B1.T
+    fd = popc(qs[:, None] ^ ws[None, :])
+    assert np.array_equal(prod, 2 * fd - 2 * t - 1)
+    assert np.array_equal(prod < 0, fd <= t)
+    assert (prod < 0).any() and (prod >= 0).any()

@@ -97,6 +97,36 @@ def load_traffic(form: str, workload: str):
     return t
 
 
+def roofline_of(st: dict, kernel_ms, variant: str, bits: int, traffic) -> dict:
+    """Roofline of the match kernel: algorithmic VALU work per launch (the
+    filter unit's VALU ops per examined pair + band cells of the survivors)
+    over the kernel's measured duration, against the int-VALU peak; on the
+    matrix cores the int8 contraction is reported beside it."""
+    matrix = st.get("filter_unit") == FPM_UNIT_MATRIX
+    per_pair = MATRIX_VALU_OPS_PER_PAIR if matrix else FILTER_OPS[(variant, bits)]
+    ops = per_pair * st["pairs_examined"] + st["verify_cells"]
+    achieved = ops / (kernel_ms * 1e-3) if kernel_ms else None
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12 if achieved else None,
+        "peak": PEAK_INT_OPS / 1e12,
+        "unit": "Tops/s",
+        "frac": achieved / PEAK_INT_OPS if achieved else None,
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "kernel": "k_match (fused filter + LDS queue + verify)",
+        "filter_unit": "matrix" if matrix else "valu",
+        "valu_ops_per_pair": per_pair,
+        "ops_per_launch": ops,
+        "kernel_ms": kernel_ms,
+    }
+    if matrix and kernel_ms:
+        m_ops = MATRIX_INT8_OPS_PER_PAIR * st["pairs_examined"]
+        roofline["matrix_cores"] = {"achieved": m_ops / (kernel_ms * 1e-3) / 1e12,
+                                    "peak": PEAK_INT8_MATRIX_OPS / 1e12, "unit": "int8 Tops/s",
+                                    "frac": m_ops / (kernel_ms * 1e-3) / PEAK_INT8_MATRIX_OPS}
+    return roofline
+
+
 def serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry):
     """With several batches in flight the best slab shifts (the match kernel
     shares the GPU with the other batches' small kernels): time the autotuned
@@ -325,29 +355,8 @@ def main():
     head = names[-1]
     r = results[head]
     st = r["stats"]
-    matrix = st.get("filter_unit") == FPM_UNIT_MATRIX
-    per_pair = MATRIX_VALU_OPS_PER_PAIR if matrix else FILTER_OPS[(args.variant, args.bits)]
-    ops = per_pair * st["pairs_examined"] + st["verify_cells"]
-    achieved = ops / (r["kernel_ms"] * 1e-3) if r["kernel_ms"] else None
     traffic = load_traffic(head, args.workload)
-    roofline = {
-        "bound": "alu",
-        "achieved": achieved / 1e12 if achieved else None,
-        "peak": PEAK_INT_OPS / 1e12,
-        "unit": "Tops/s",
-        "frac": achieved / PEAK_INT_OPS if achieved else None,
-        "traffic": traffic["bytes_per_launch"] if traffic else None,
-        "kernel": "k_match (fused filter + LDS queue + verify)",
-        "filter_unit": "matrix" if matrix else "valu",
-        "valu_ops_per_pair": per_pair,
-        "ops_per_launch": ops,
-        "kernel_ms": r["kernel_ms"],
-    }
-    if matrix and r["kernel_ms"]:
-        m_ops = MATRIX_INT8_OPS_PER_PAIR * st["pairs_examined"]
-        roofline["matrix_cores"] = {"achieved": m_ops / (r["kernel_ms"] * 1e-3) / 1e12,
-                                    "peak": PEAK_INT8_MATRIX_OPS / 1e12, "unit": "int8 Tops/s",
-                                    "frac": m_ops / (r["kernel_ms"] * 1e-3) / PEAK_INT8_MATRIX_OPS}
+    roofline = roofline_of(st, r["kernel_ms"], args.variant, args.bits, traffic)
 
     cpu = None
     sampled_parity = None

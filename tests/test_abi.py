@@ -67,3 +67,31 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_roofline_follows_the_filter_unit():
+    """The bench prices the match kernel with the VALU work of the unit that
+    ran the filter (fpm_stats.filter_unit): 3 ops per examined occ16 pair on
+    the vector ALUs, 1 (the sign-bit shift) on the matrix cores, where the
+    int8 contraction (64 ops per pair) is reported against the matrix peak."""
+    import sys as _sys
+
+    _sys.path.insert(0, ROOT)
+    import bench
+    from paper_1711_08475_amd import fpm as f
+
+    st = {"pairs_examined": 1_000_000, "verify_cells": 500_000, "filter_unit": f.FPM_UNIT_VALU}
+    r = bench.roofline_of(st, 0.001, "occ", 16, None)
+    assert r["filter_unit"] == "valu" and r["valu_ops_per_pair"] == 3
+    assert r["ops_per_launch"] == 3_500_000
+    assert abs(r["achieved"] - 3.5e6 / 1e-6 / 1e12) < 1e-9
+    assert abs(r["frac"] - 3.5e12 / (256 * 64 * 2.4e9)) < 1e-12
+    assert "matrix_cores" not in r and r["traffic"] is None and r["bound"] == "alu"
+    st["filter_unit"] = f.FPM_UNIT_MATRIX
+    r = bench.roofline_of(st, 0.001, "occ", 16, {"bytes_per_launch": 123})
+    assert r["filter_unit"] == "matrix" and r["valu_ops_per_pair"] == 1
+    assert r["ops_per_launch"] == 1_500_000 and r["traffic"] == 123
+    assert abs(r["matrix_cores"]["frac"] - 64e6 / 1e-6 / 5.0e15) < 1e-12
+    # no kernel time: nothing achieved, nothing divided by zero
+    r = bench.roofline_of(st, None, "occ", 16, None)
+    assert r["achieved"] is None and r["frac"] is None and "matrix_cores" not in r

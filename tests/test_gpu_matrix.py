@@ -184,12 +184,20 @@ def test_matrix_unit_errors(fpm, small):
 
 def test_matrix_full_size_sampled_parity(fpm):
     """english_1m_q10k with the learned grouping (occ16, Lev k = 1) in the
-    benchmark's launch configuration (batched, persistent, hipGraph, tuned
-    tiles): the matrix and vector paths return the same match list and
-    survivor count, and sampled query rows equal the oracle's."""
+    benchmark's launch configuration (batched, persistent, hipGraph, the
+    tiles of the tuning table's headline entry): the matrix and vector paths
+    return the same match list and survivor count, and sampled query rows
+    equal the oracle's."""
+    import json
+    import os
+
     import torch
 
     from paper_1711_08475_amd import learn
+
+    table = json.load(open(os.path.join(os.path.dirname(learn.__file__), "tuned.json")))
+    entry = dict(table["english_1m_q10k|occ16|lev1|learned"])
+    entry.pop("inflight", None)
 
     d, q = datagen.workload("english_1m_q10k")
     nq = q[1].size - 1
@@ -201,9 +209,7 @@ def test_matrix_full_size_sampled_parity(fpm):
     torch.cuda.synchronize()
     res = {}
     for unit in ("matrix", "valu"):
-        plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), oracle.LEV, 1,
-                                   fpm.options(schedule=1, queries_per_item=128, slab=1024, bucket_order=1,
-                                               filter_unit=unit))
+        plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), oracle.LEV, 1, fpm.options(**entry, filter_unit=unit))
         fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
         res[unit] = (fpm.fpm_plan_copy_matches(plan), fpm.fpm_plan_result(plan)[2])
         del plan

@@ -47,6 +47,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=41)
+    ap.add_argument("--filter-unit", default="auto", choices=["auto", "valu", "matrix"],
+                    help="where the filter test runs (fpm_options.filter_unit)")
     args = ap.parse_args(argv)
 
     import torch
@@ -73,7 +75,8 @@ def main(argv=None):
                 brute_ms, _ = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
                 ref = fpm.fpm_plan_copy_matches(plan)
                 del plan
-            best, _ = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "ham", 1, 2)
+            best, _ = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "ham", 1, 2,
+                                       base=fpm.options(filter_unit=args.filter_unit))
             plan = fpm.fpm_plan_create(ix, nq, qbytes, "ham", 1, best)
             ms, st = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
             got = fpm.fpm_plan_copy_matches(plan)
@@ -89,6 +92,7 @@ def main(argv=None):
                 "brute_ms": brute_ms,
                 "speedup": brute_ms / ms,
                 "rejection_rate": 1.0 - st["survivors"] / max(st["pairs_examined"], 1),
+                "filter_unit": {1: "valu", 2: "matrix"}.get(st.get("filter_unit"), "none"),
                 "pairs_per_s": nq * args.words / (ms * 1e-3),
                 "matches": int(got.shape[0]),
                 "tiles": [best.queries_per_item, best.slab, best.bucket_order, best.tail_split],

@@ -97,11 +97,12 @@ def load_traffic(form: str, workload: str):
     return t
 
 
-def roofline_of(st: dict, kernel_ms, variant: str, bits: int, traffic) -> dict:
+def roofline_of(st: dict, kernel_ms, variant: str, bits: int, traffic, peaks=None) -> dict:
     """Roofline of the match kernel: algorithmic VALU work per launch (the
     filter unit's VALU ops per examined pair + band cells of the survivors)
-    over the kernel's measured duration, against the int-VALU peak; on the
-    matrix cores the int8 contraction is reported beside it."""
+    over the kernel's measured duration, against the published int-VALU
+    peak; on the matrix cores the int8 contraction is reported beside it.
+    `peaks` (fpm_measure_peaks) adds the peaks measured on this device."""
     matrix = st.get("filter_unit") == FPM_UNIT_MATRIX
     per_pair = MATRIX_VALU_OPS_PER_PAIR if matrix else FILTER_OPS[(variant, bits)]
     ops = per_pair * st["pairs_examined"] + st["verify_cells"]
@@ -119,11 +120,15 @@ def roofline_of(st: dict, kernel_ms, variant: str, bits: int, traffic) -> dict:
         "ops_per_launch": ops,
         "kernel_ms": kernel_ms,
     }
+    if peaks:
+        roofline["peak_measured"] = peaks["int_valu_ops_per_s"] / 1e12
     if matrix and kernel_ms:
         m_ops = MATRIX_INT8_OPS_PER_PAIR * st["pairs_examined"]
         roofline["matrix_cores"] = {"achieved": m_ops / (kernel_ms * 1e-3) / 1e12,
                                     "peak": PEAK_INT8_MATRIX_OPS / 1e12, "unit": "int8 Tops/s",
                                     "frac": m_ops / (kernel_ms * 1e-3) / PEAK_INT8_MATRIX_OPS}
+        if peaks:
+            roofline["matrix_cores"]["peak_measured"] = peaks["int8_matrix_ops_per_s"] / 1e12
     return roofline
 
 
@@ -356,7 +361,10 @@ def main():
     r = results[head]
     st = r["stats"]
     traffic = load_traffic(head, args.workload)
-    roofline = roofline_of(st, r["kernel_ms"], args.variant, args.bits, traffic)
+    peaks = fpm.fpm_measure_peaks()  # the device's own peak rates, reported beside the published ones
+    log(f"measured peaks: int VALU {peaks['int_valu_ops_per_s'] / 1e12:.2f} Tops/s, "
+        f"int8 matrix {peaks['int8_matrix_ops_per_s'] / 1e12:.0f} Tops/s")
+    roofline = roofline_of(st, r["kernel_ms"], args.variant, args.bits, traffic, peaks)
 
     cpu = None
     sampled_parity = None

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfpm.so")
-SOURCES = ["fpm_build.hip", "fpm_sort.hip", "fpm_match.hip", "fpm_api.hip", "fpm_learn.hip"]
+SOURCES = ["fpm_build.hip", "fpm_sort.hip", "fpm_match.hip", "fpm_api.hip", "fpm_learn.hip", "fpm_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

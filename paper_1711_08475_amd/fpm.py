@@ -43,6 +43,8 @@ EXPORTS = [
 ]
 # every symbol include/fpm_learn.h declares
 LEARN_EXPORTS = ["fpm_learn_grouping", "fpm_learn_step"]
+# every symbol include/fpm_peak.h declares
+PEAK_EXPORTS = ["fpm_measure_peaks"]
 
 
 class FpmError(RuntimeError):
@@ -70,6 +72,15 @@ class Options(ctypes.Structure):
                 ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
                 ("tail_split", ctypes.c_uint32), ("bound", ctypes.c_uint32), ("filter_unit", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 5)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Peaks(ctypes.Structure):
+    _fields_ = [("int_valu_ops_per_s", ctypes.c_double), ("int8_matrix_ops_per_s", ctypes.c_double),
+                ("valu_ops", ctypes.c_uint64), ("matrix_ops", ctypes.c_uint64), ("valu_ms", ctypes.c_float),
+                ("matrix_ms", ctypes.c_float), ("compute_units", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -158,6 +169,7 @@ def lib():
     sig["fpm_learn_step"] = (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_uint32, fp, fp, u64p, u64p, ctypes.c_uint64, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, fp, fp, fp])
+    sig["fpm_measure_peaks"] = (ctypes.c_int, [ctypes.POINTER(Peaks)])
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
@@ -397,3 +409,12 @@ def fpm_learn_step(X, params, hidden: int, bits: int, k: int, masks_a, masks_b, 
                                 _p(mb, ctypes.c_uint64), ma.shape[0], margin, beta, entropy_weight, _p(P, fp),
                                 _p(loss, fp), _p(g, fp)))
     return P, loss, g
+
+
+# ------------------------------------------------------------ peak probes
+
+def fpm_measure_peaks() -> dict:
+    """Measured int-VALU and int8 matrix-core peaks of the current device."""
+    out = Peaks()
+    _check(lib().fpm_measure_peaks(ctypes.byref(out)))
+    return out.as_dict()

@@ -24,7 +24,7 @@ def test_header_declares_the_boundary():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libfpm.so not built")
-@pytest.mark.parametrize("header", ["fpm.h", "fpm_learn.h"])
+@pytest.mark.parametrize("header", ["fpm.h", "fpm_learn.h", "fpm_peak.h"])
 def test_library_exports_every_declared_symbol(header):
     lib = ctypes.CDLL(LIB)
     names = declared(header)
@@ -39,7 +39,8 @@ def test_binding_names_match_header():
 
     assert sorted(fpm.EXPORTS) == declared("fpm.h")
     assert sorted(fpm.LEARN_EXPORTS) == declared("fpm_learn.h")
-    for n in fpm.EXPORTS + fpm.LEARN_EXPORTS:
+    assert sorted(fpm.PEAK_EXPORTS) == declared("fpm_peak.h")
+    for n in fpm.EXPORTS + fpm.LEARN_EXPORTS + fpm.PEAK_EXPORTS:
         if n in ("fpm_last_error", "fpm_free", "fpm_index_destroy", "fpm_plan_destroy"):
             continue
         assert callable(getattr(fpm, n)), n
@@ -92,6 +93,10 @@ def test_bench_roofline_follows_the_filter_unit():
     assert r["filter_unit"] == "matrix" and r["valu_ops_per_pair"] == 1
     assert r["ops_per_launch"] == 1_500_000 and r["traffic"] == 123
     assert abs(r["matrix_cores"]["frac"] - 64e6 / 1e-6 / 5.0e15) < 1e-12
+    r = bench.roofline_of(st, 0.001, "occ", 16, None, {"int_valu_ops_per_s": 4.0e13,
+                                                        "int8_matrix_ops_per_s": 4.5e15})
+    assert abs(r["peak_measured"] - 40.0) < 1e-9 and abs(r["matrix_cores"]["peak_measured"] - 4500.0) < 1e-9
+    assert abs(r["peak"] - 39.3216) < 1e-9  # the published peak stays the reference
     # no kernel time: nothing achieved, nothing divided by zero
     r = bench.roofline_of(st, None, "occ", 16, None)
     assert r["achieved"] is None and r["frac"] is None and "matrix_cores" not in r

@@ -280,3 +280,44 @@ def test_matrix_url_full_size_sampled_parity(fpm):
     ref[:, 0] = sample[ref[:, 0]]
     got = res["matrix"][0]
     assert np.array_equal(got[np.isin(got[:, 0], sample)], ref)
+
+
+def test_matrix_plan_graph_replays_and_batches_in_flight(fpm, small):
+    """One batched plan (hipGraph on) replayed several times on two query
+    batches (the graph is re-captured when the batch changes and replayed
+    otherwise), with eager device work and synchronisations between the
+    replays; then two plans on their own streams taking alternate batches
+    without waiting for each other.  Every result equals the oracle's."""
+    import torch
+
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    half = datagen.take_csr(q, np.arange(0, q[1].size - 1, 2))
+    batches = []
+    for qq in (q, half):
+        qb = torch.from_numpy(qq[0].copy()).cuda()
+        qo = torch.from_numpy(qq[1].view(np.int64).copy()).cuda()
+        batches.append((qq, qb, qo, qq[1].size - 1, oracle.match(d, qq, oracle.LEV, 1)))
+    torch.cuda.synchronize()
+    nq_max, bytes_max = q[1].size - 1, int(q[1][-1])
+    opts = fpm.options(schedule=1, filter_unit="matrix", queries_per_item=64, slab=512)
+    plan = fpm.fpm_plan_create(ix, nq_max, bytes_max, oracle.LEV, 1, opts)
+    x = torch.ones(512, 512, device="cuda")
+    for i, b in enumerate([0, 0, 0, 1, 1, 0, 1, 0]):
+        say("matrix graph replay", i, "batch", b)
+        _, qb, qo, nq, ref = batches[b]
+        fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+        x = (x @ x).clamp_(max=1.0)  # eager work on the default stream between replays
+        torch.cuda.synchronize()
+        got = fpm.fpm_plan_copy_matches(plan)
+        assert np.array_equal(got, ref)
+        assert fpm.fpm_plan_result(plan)[2]["filter_unit"] == fpm.FPM_UNIT_MATRIX
+    del plan
+    plans = [fpm.fpm_plan_create(ix, nq_max, bytes_max, oracle.LEV, 1, opts) for _ in range(2)]
+    for rnd in range(3):
+        say("matrix plans in flight", rnd)
+        for j, p in enumerate(plans):
+            _, qb, qo, nq, _ = batches[(j + rnd) % 2]
+            fpm.fpm_plan_run(p, qb.data_ptr(), qo.data_ptr(), nq)
+        for j, p in enumerate(plans):
+            assert np.array_equal(fpm.fpm_plan_copy_matches(p), batches[(j + rnd) % 2][4])

@@ -19,7 +19,11 @@
 //   msk = (msk << 1) | (t >> 31)         one v_alignbit: sign bit = F_D <= 2k
 // i.e. three vector instructions per (query, word) pair (other key
 // families: position fields 8, bigrams 3 against 4k, the asymmetric bound 3
-// or 4, 64-bit keys 5 or 6).  Under the asymmetric bound the query and word
+// or 4, 64-bit keys 5 or 6).  On the matrix cores (16- and 32-bit
+// popcount-of-XOR keys, the matrix-filter section below) a pass is instead
+// 64 queries x 64 words (32-bit keys: x 32) computed as an int8 matrix
+// product whose sign bits land in masks of the same layout, one
+// v_alignbit per 64 pairs.  Under the asymmetric bound the query and word
 // blocks are ordered by key popcount, and items and 32 x 128 passes whose
 // popcount ranges cannot meet are skipped.  Each of the lane's
 // two 32-bit survivor masks is then appended to a per-wave queue in LDS:

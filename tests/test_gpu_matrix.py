@@ -321,3 +321,21 @@ def test_matrix_plan_graph_replays_and_batches_in_flight(fpm, small):
             fpm.fpm_plan_run(p, qb.data_ptr(), qo.data_ptr(), nq)
         for j, p in enumerate(plans):
             assert np.array_equal(fpm.fpm_plan_copy_matches(p), batches[(j + rnd) % 2][4])
+
+
+@pytest.mark.parametrize("which", ["url", "mixed"])
+@pytest.mark.parametrize("variant,metric,k", [("occ", oracle.LEV, 1), ("occ", oracle.LEV, 2), ("occ", oracle.HAM, 1),
+                                              ("occh", oracle.HAM, 2), ("qgram", oracle.LEV, 1)])
+def test_matrix_long_strings(fpm, which, variant, metric, k):
+    """URL-like strings (lengths 20-120, shared host and path vocabulary) and
+    a mixed English / URL set through the matrix filter with 16-bit keys:
+    match sets and survivor counts equal the oracle's."""
+    d, q = datagen.url_workload(4000, 300, 5, 0.3, (1, 2)) if which == "url" else \
+        datagen.mixed_workload(2000, 2000, 300, 9)
+    say("matrix long strings", which, variant, metric, k)
+    ix = fpm.fpm_build_fingerprints(d, variant, 16, "mixed" if which == "url" else "common")
+    for sched in (0, 1):
+        got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=sched, filter_unit="matrix"),
+                                with_stats=True)
+        assert np.array_equal(got, ref_match(which, d, q, metric, k))
+        assert st["survivors"] == oracle_survivors(d, q, variant, fpm.fpm_get_map(ix), metric, k)

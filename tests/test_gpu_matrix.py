@@ -339,3 +339,25 @@ def test_matrix_long_strings(fpm, which, variant, metric, k):
                                 with_stats=True)
         assert np.array_equal(got, ref_match(which, d, q, metric, k))
         assert st["survivors"] == oracle_survivors(d, q, variant, fpm.fpm_get_map(ix), metric, k)
+
+
+def test_matrix_autotune_keeps_the_unit(fpm, small):
+    """fpm_autotune searches tiles around a base whose filter unit is the
+    matrix cores: the returned options keep the unit, and a plan built from
+    them runs on the matrix cores and matches the oracle."""
+    import torch
+
+    d, q = small
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()
+    nq = q[1].size - 1
+    say("matrix autotune")
+    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, int(q[1][-1]), "lev", 1, 1,
+                                  base=fpm.options(filter_unit="matrix"))
+    assert rows and best.filter_unit == fpm.FPM_UNIT_MATRIX
+    plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, best)
+    fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+    assert fpm.fpm_plan_result(plan)[2]["filter_unit"] == fpm.FPM_UNIT_MATRIX
+    assert np.array_equal(fpm.fpm_plan_copy_matches(plan), ref_match("small", d, q, oracle.LEV, 1))

@@ -108,12 +108,12 @@ typedef enum { FPM_SCHED_PLAIN = 0, FPM_SCHED_BATCHED = 1, FPM_SCHED_BRUTE = 2 }
 typedef enum { FPM_BOUND_FD = 0, FPM_BOUND_ASYM = 1 } fpm_bound;
 
 /* Where the filter test F_D <= t (Eq. 1; t = 2k, bigrams 4k) runs.
- *   FPM_UNIT_AUTO (default): on the matrix cores for 16-bit occurrence,
- *     occurrence-halved and bigram keys under the paper's rule (where they
- *     are faster), else on the vector ALUs.
- *   FPM_UNIT_VALU: vector ALUs only -- per pair one XOR, one popcount and
- *     one shift of the result's sign bit into a survivor mask.
- *   FPM_UNIT_MATRIX: matrix cores; FPM_EUNSUPPORTED where the key family
+ *   FPM_UNIT_AUTO (default) = FPM_UNIT_VALU.
+ *   FPM_UNIT_VALU: vector ALUs -- per pair one XOR, one popcount and one
+ *     shift of the result's sign bit into a survivor mask.
+ *   FPM_UNIT_MATRIX (opt-in, an addition of this library: the method is
+ *     integer bit arithmetic and the paper's design has no matrix unit):
+ *     matrix cores; FPM_EUNSUPPORTED where the key family
  *     does not allow it.  F_D of two bit vectors is an inner product: with
  *     every key bit written as a signed byte (+1 for 0, -1 for 1 on the
  *     query side, the negation on the word side), the product of a query
@@ -216,6 +216,24 @@ fpm_status fpm_get_map(const fpm_index *ix, uint8_t map_out[256]);
 
 /* Number of words, variant and fingerprint bits of an index. */
 fpm_status fpm_index_info(const fpm_index *ix, uint32_t *n_words, uint32_t *variant, uint32_t *bits);
+
+/* Device time of the index build (the preprocessing of Section 3.4; the
+ * paper reports its fingerprint construction speed in Table 4), measured
+ * with HIP events once the dictionary is resident on the device:
+ * *total_ms = symbol statistics + length sort + padded layout with
+ * fingerprints + inverse permutation; *layout_ms = the last three.  Either
+ * pointer may be NULL. */
+fpm_status fpm_index_build_ms(const fpm_index *ix, float *total_ms, float *layout_ms);
+
+/* Device memory accounting.  Every device buffer the library allocates
+ * (indexes, plans, the temporaries of the host-buffer calls, the learned
+ * grouping) counts against one process-wide total.  With a limit set, an
+ * allocation that would take the total past it fails with FPM_ENOMEM before
+ * any device call, and the failing entry point releases what it had taken.
+ * max_bytes = 0 removes the limit (the default).  Buffers allocated before a
+ * limit was set stay valid. */
+fpm_status fpm_set_device_memory_limit(uint64_t max_bytes);
+fpm_status fpm_device_memory_in_use(uint64_t *bytes);
 
 /* Fingerprints of arbitrary strings under the index's map and variant
  * (Section 3.2), caller's order, widened to uint32.  Host buffers. */

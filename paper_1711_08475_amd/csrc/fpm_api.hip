@@ -11,8 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/fpm.h"
@@ -39,6 +41,49 @@ fpm_status fail(fpm_status st, const char *fmt, ...)
 fpm_status hip_fail(hipError_t e, const char *what)
 {
     return fail(e == hipErrorOutOfMemory ? FPM_ENOMEM : FPM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+struct DeviceMemory {
+    std::mutex mu;
+    std::unordered_map<void *, size_t> live;
+    uint64_t in_use = 0;
+    uint64_t limit = 0;  // 0: no limit
+};
+DeviceMemory &device_memory()
+{
+    static DeviceMemory *m = new DeviceMemory();  // never destroyed: buffers may be freed at process exit
+    return *m;
+}
+}  // namespace
+
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    DeviceMemory &m = device_memory();
+    std::lock_guard<std::mutex> g(m.mu);
+    *p = nullptr;
+    if (m.limit && m.in_use + bytes > m.limit)
+        return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    m.live[*p] = bytes;
+    m.in_use += bytes;
+    return hipSuccess;
+}
+
+void dev_free(void *p)
+{
+    DeviceMemory &m = device_memory();
+    std::lock_guard<std::mutex> g(m.mu);
+    auto it = m.live.find(p);
+    if (it != m.live.end()) {
+        m.in_use -= it->second;
+        m.live.erase(it);
+    }
+    (void)hipFree(p);
 }
 
 }  // namespace fpm
@@ -207,6 +252,9 @@ struct fpm_index {
     uint32_t h_off[257];
     uint32_t wbits = 1;
     int device = 0;
+    uint64_t bytes = 0;     // dictionary bytes
+    float build_ms = 0.f;   // device time of the build (symbol statistics .. inverse permutation)
+    float layout_ms = 0.f;  // of that: length sort, padded layout and fingerprints
 };
 
 struct fpm_plan {
@@ -270,15 +318,28 @@ struct fpm_plan {
         g_valid = false;
     }
 
+    // (Re)allocates the match buffers for cap_entries matches.  The new
+    // buffers are taken before the old ones are released, so on failure the
+    // plan keeps its previous buffers and capacity and stays usable.  Called
+    // only while nothing runs on the plan's stream.
     fpm_status alloc_output(uint64_t cap_entries)
     {
+        uint64_t *k2 = nullptr, *t2 = nullptr;
+        uint32_t *tr2 = nullptr;
+        hipError_t e;
+        if ((e = dalloc(&k2, cap_entries)) || (e = dalloc(&t2, cap_entries)) || (e = dalloc(&tr2, cap_entries * 3))) {
+            dfree(k2);
+            dfree(t2);
+            dfree(tr2);
+            return hip_fail(e, "match buffer allocation");
+        }
         dfree(keys);
         dfree(tmp);
         dfree(triples);
+        keys = k2;
+        tmp = t2;
+        triples = tr2;
         cap = cap_entries;
-        HIPCHK(dalloc(&keys, cap));
-        HIPCHK(dalloc(&tmp, cap));
-        HIPCHK(dalloc(&triples, cap * 3));
         drop_graphs();
         return FPM_OK;
     }
@@ -420,29 +481,42 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
         if (s)
             (void)hipStreamDestroy(s);
     };
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    auto cleanup_events = [&]() {
+        for (hipEvent_t &v : ev)
+            if (v)
+                (void)hipEventDestroy(v);
+    };
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = dalloc(&d_bytes, nbytes + 4)) ||
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || (e = hipEventCreate(&ev[0])) ||
+        (e = hipEventCreate(&ev[1])) || (e = hipEventCreate(&ev[2])) || (e = dalloc(&d_bytes, nbytes + 4)) ||
         (e = dalloc(&d_off, (size_t)n_words + 1)) || (e = dalloc(&d_hist, 256)) ||
         (e = dalloc(&scratch, kRadixScratch)) || (e = dalloc(&d_err, 1)) || (e = dalloc(&ix->d_map, 256)) ||
         (e = ix->words.alloc(n_words, nbytes, ix->kind, true, true, false))) {
+        cleanup_events();
         cleanup();
         fpm_index_destroy(ix);
         return hip_fail(e, "fpm_build_fingerprints alloc");
     }
+    ix->bytes = nbytes;
+    if (symbols == FPM_CUSTOM)
+        (void)hipMemcpyAsync(ix->d_map, custom_map, 256, hipMemcpyHostToDevice, s);
     if (nbytes)
         (void)hipMemcpyAsync(d_bytes, bytes, nbytes, hipMemcpyHostToDevice, s);
     (void)hipMemcpyAsync(d_off, offsets, sizeof(uint64_t) * ((size_t)n_words + 1), hipMemcpyHostToDevice, s);
+    // the device part of the build, timed from here (inputs resident)
+    (void)hipEventRecord(ev[0], s);
     launch_zero(d_err, 1, s);
-    if (symbols == FPM_CUSTOM) {
-        (void)hipMemcpyAsync(ix->d_map, custom_map, 256, hipMemcpyHostToDevice, s);
-    } else {
+    if (symbols != FPM_CUSTOM) {
         launch_zero(d_hist, 512, s);
         launch_byte_histogram(d_bytes, d_off, n_words, d_hist, s);
         launch_select_symbols(d_hist, nf, (int)symbols, ix->d_map, s);
     }
+    (void)hipEventRecord(ev[1], s);
     prep_strings(ix->words, d_bytes, d_off, n_words, nbytes, ix->d_map, variant, bits, ix->kind, true, false, d_err,
                  scratch, s);
     launch_invert(ix->words.perm, n_words, ix->words.inv, s);
+    (void)hipEventRecord(ev[2], s);
     uint32_t h_err = 0;
     (void)hipMemcpyAsync(ix->map, ix->d_map, 256, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(ix->h_off, ix->words.off, sizeof(uint32_t) * 257, hipMemcpyDeviceToHost, s);
@@ -450,6 +524,11 @@ fpm_status fpm_build_fingerprints(const uint8_t *bytes, const uint64_t *offsets,
     e = hipStreamSynchronize(s);
     if (!e)
         e = hipGetLastError();
+    if (!e)
+        e = hipEventElapsedTime(&ix->build_ms, ev[0], ev[2]);
+    if (!e)
+        e = hipEventElapsedTime(&ix->layout_ms, ev[1], ev[2]);
+    cleanup_events();
     cleanup();
     if (e) {
         fpm_index_destroy(ix);
@@ -479,6 +558,38 @@ fpm_status fpm_get_map(const fpm_index *ix, uint8_t map_out[256])
     if (!ix || !map_out)
         return fail(FPM_EINVAL, "null pointer");
     memcpy(map_out, ix->map, 256);
+    return FPM_OK;
+}
+
+fpm_status fpm_index_build_ms(const fpm_index *ix, float *total_ms, float *layout_ms)
+{
+    g_last_error.clear();
+    if (!ix)
+        return fail(FPM_EINVAL, "null index");
+    if (total_ms)
+        *total_ms = ix->build_ms;
+    if (layout_ms)
+        *layout_ms = ix->layout_ms;
+    return FPM_OK;
+}
+
+fpm_status fpm_set_device_memory_limit(uint64_t max_bytes)
+{
+    g_last_error.clear();
+    DeviceMemory &m = device_memory();
+    std::lock_guard<std::mutex> g(m.mu);
+    m.limit = max_bytes;
+    return FPM_OK;
+}
+
+fpm_status fpm_device_memory_in_use(uint64_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes)
+        return fail(FPM_EINVAL, "null pointer");
+    DeviceMemory &m = device_memory();
+    std::lock_guard<std::mutex> g(m.mu);
+    *bytes = m.in_use;
     return FPM_OK;
 }
 
@@ -651,12 +762,10 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on occurrence, "
                                       "occurrence-halved, 16-bit count and bigram fingerprints");
     }
-    // auto: matrix cores for 16-bit keys only (32-bit tiles carry half the
-    // pairs per pass and four times the query-row loads per pair; measured
-    // slower than the vector filter on every 32-bit workload)
+    // auto: the vector ALUs (the method is integer bit arithmetic); the
+    // matrix cores only when asked for
     const int key_width = ix->bits == 16 && ix->variant != FPM_COUNT ? 16 : 32;
-    const bool want = p->opt.filter_unit == FPM_UNIT_MATRIX || (p->opt.filter_unit == FPM_UNIT_AUTO && key_width == 16);
-    p->mx_width = mx_ok && want ? key_width : 0;
+    p->mx_width = mx_ok && p->opt.filter_unit == FPM_UNIT_MATRIX ? key_width : 0;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;

@@ -16,18 +16,25 @@ extern thread_local std::string g_last_error;
 fpm_status fail(fpm_status st, const char *fmt, ...);
 fpm_status hip_fail(hipError_t e, const char *what);
 
+// Every device buffer of the library goes through these two: they keep the
+// process-wide count of live bytes that fpm_device_memory_in_use reports,
+// and refuse an allocation that would take it past the limit set with
+// fpm_set_device_memory_limit (hipErrorOutOfMemory, i.e. FPM_ENOMEM).
+hipError_t dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+
 template <typename T>
 hipError_t dalloc(T **p, size_t count)
 {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-    return hipMalloc((void **)p, bytes);
+    return dev_alloc((void **)p, bytes);
 }
 
 template <typename T>
 void dfree(T *&p)
 {
     if (p)
-        (void)hipFree((void *)p);
+        dev_free((void *)p);
     p = nullptr;
 }
 

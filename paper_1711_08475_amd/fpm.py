@@ -39,7 +39,8 @@ EXPORTS = [
     "fpm_last_error", "fpm_free", "fpm_num_fields", "fpm_select_symbols", "fpm_build_fingerprints",
     "fpm_index_destroy", "fpm_get_fingerprints", "fpm_get_map", "fpm_index_info", "fpm_fingerprints",
     "fpm_match", "fpm_filter_pairs", "fpm_verify_pairs", "fpm_plan_create", "fpm_plan_run", "fpm_plan_result",
-    "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune", "fpm_plan_kernel_ms",
+    "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune", "fpm_plan_kernel_ms", "fpm_index_build_ms",
+    "fpm_set_device_memory_limit", "fpm_device_memory_in_use",
 ]
 # every symbol include/fpm_learn.h declares
 LEARN_EXPORTS = ["fpm_learn_grouping", "fpm_learn_step"]
@@ -143,6 +144,9 @@ def lib():
         "fpm_get_fingerprints": (ctypes.c_int, [vp, u32p]),
         "fpm_get_map": (ctypes.c_int, [vp, u8p]),
         "fpm_index_info": (ctypes.c_int, [vp, u32p, u32p, u32p]),
+        "fpm_index_build_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+        "fpm_set_device_memory_limit": (ctypes.c_int, [ctypes.c_uint64]),
+        "fpm_device_memory_in_use": (ctypes.c_int, [u64p]),
         "fpm_fingerprints": (ctypes.c_int, [vp, u8p, u64p, ctypes.c_uint32, u32p]),
         "fpm_match": (ctypes.c_int, [vp, u8p, u64p, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
                                      ctypes.POINTER(Options), ctypes.POINTER(ctypes.POINTER(Hit)), u64p,
@@ -260,6 +264,23 @@ def fpm_index_info(ix: Index):
     n, v, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().fpm_index_info(ix.handle, ctypes.byref(n), ctypes.byref(v), ctypes.byref(b)))
     return n.value, v.value, b.value
+
+
+def fpm_index_build_ms(ix: Index):
+    """(total, layout) device ms of the index build."""
+    t, l = ctypes.c_float(), ctypes.c_float()
+    _check(lib().fpm_index_build_ms(ix.handle, ctypes.byref(t), ctypes.byref(l)))
+    return t.value, l.value
+
+
+def fpm_set_device_memory_limit(max_bytes: int):
+    _check(lib().fpm_set_device_memory_limit(max_bytes))
+
+
+def fpm_device_memory_in_use() -> int:
+    n = ctypes.c_uint64()
+    _check(lib().fpm_device_memory_in_use(ctypes.byref(n)))
+    return n.value
 
 
 def fpm_fingerprints(ix: Index, csr) -> np.ndarray:

@@ -70,32 +70,44 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
-def test_bench_roofline_follows_the_filter_unit():
-    """The bench prices the match kernel with the VALU work of the unit that
-    ran the filter (fpm_stats.filter_unit): 3 ops per examined occ16 pair on
-    the vector ALUs, 1 (the sign-bit shift) on the matrix cores, where the
-    int8 contraction (64 ops per pair) is reported against the matrix peak."""
+def test_bench_roofline_prices_the_methods_work():
+    """The bench prices the match kernel with the method's algorithmic work,
+    whichever unit ran the filter test: filter ops per examined pair (occ 3,
+    count16 3, count32 5, pos 9) x examined pairs + (2k+1) min(m, n) band
+    cells of the survivors, over the kernel's duration, against the published
+    int-VALU peak.  Issued-VALU utilisation and the matrix-core int8 fraction
+    are reported beside it under their own names."""
     import sys as _sys
 
     _sys.path.insert(0, ROOT)
     import bench
     from paper_1711_08475_amd import fpm as f
 
+    assert [bench.filter_ops(v, b) for v, b in [("occ", 16), ("occ", 32), ("count", 16), ("count", 32),
+                                                 ("pos", 16), ("occh", 16), ("qgram", 32), ("combo", 32)]] == \
+        [3, 3, 3, 5, 9, 3, 3, 6]
+    # 1M English-like words x 10K queries, learned occ16, Lev k = 1: 4.186e9
+    # examined pairs, 2.321e9 band cells, match kernel 0.5894 ms (matrix
+    # cores ran the filter): 1.488e10 ops / 0.5894 ms / 39.32 Tops/s = 0.64
+    st = {"pairs_examined": 4_186_148_656, "verify_cells": 2_321_000_000, "filter_unit": f.FPM_UNIT_MATRIX}
+    r = bench.roofline_of(st, 0.5894, "occ", 16, None)
+    assert r["filter_unit"] == "matrix" and r["filter_ops_per_pair"] == 3
+    assert r["ops_per_launch"] == 3 * 4_186_148_656 + 2_321_000_000
+    assert abs(r["frac"] - 0.642) < 0.002
+    assert abs(r["matrix_cores"]["frac"] - 64 * 4_186_148_656 / 0.5894e-3 / 5.0e15) < 1e-12
+    st["filter_unit"] = f.FPM_UNIT_VALU
+    r2 = bench.roofline_of(st, 0.5894, "occ", 16, {"bytes_per_launch": 123, "valu_insts_per_launch": 2.93e8},
+                           hbm_bytes=19_000_000)
+    assert r2["frac"] == r["frac"] and "matrix_cores" not in r2 and r2["traffic"] == 123
+    assert abs(r2["valu_issue"]["utilisation"] - 2.93e8 / (256 * 4 * 2.4e9 / 4 * 0.5894e-3)) < 1e-12
+    assert abs(r2["hbm"]["frac"] - 19e6 / 0.5894e-3 / 8e12) < 1e-12
     st = {"pairs_examined": 1_000_000, "verify_cells": 500_000, "filter_unit": f.FPM_UNIT_VALU}
-    r = bench.roofline_of(st, 0.001, "occ", 16, None)
-    assert r["filter_unit"] == "valu" and r["valu_ops_per_pair"] == 3
-    assert r["ops_per_launch"] == 3_500_000
-    assert abs(r["achieved"] - 3.5e6 / 1e-6 / 1e12) < 1e-9
-    assert abs(r["frac"] - 3.5e12 / (256 * 64 * 2.4e9)) < 1e-12
-    assert "matrix_cores" not in r and r["traffic"] is None and r["bound"] == "alu"
-    st["filter_unit"] = f.FPM_UNIT_MATRIX
-    r = bench.roofline_of(st, 0.001, "occ", 16, {"bytes_per_launch": 123})
-    assert r["filter_unit"] == "matrix" and r["valu_ops_per_pair"] == 1
-    assert r["ops_per_launch"] == 1_500_000 and r["traffic"] == 123
-    assert abs(r["matrix_cores"]["frac"] - 64e6 / 1e-6 / 5.0e15) < 1e-12
+    r = bench.roofline_of(st, 0.001, "count", 32, None)
+    assert r["ops_per_launch"] == 5_500_000 and r["bound"] == "alu"
+    assert abs(r["achieved"] - 5.5e6 / 1e-6 / 1e12) < 1e-9
     r = bench.roofline_of(st, 0.001, "occ", 16, None, {"int_valu_ops_per_s": 4.0e13,
                                                         "int8_matrix_ops_per_s": 4.5e15})
-    assert abs(r["peak_measured"] - 40.0) < 1e-9 and abs(r["matrix_cores"]["peak_measured"] - 4500.0) < 1e-9
+    assert abs(r["peak_measured"] - 40.0) < 1e-9
     assert abs(r["peak"] - 39.3216) < 1e-9  # the published peak stays the reference
     # no kernel time: nothing achieved, nothing divided by zero
     r = bench.roofline_of(st, None, "occ", 16, None)

@@ -196,7 +196,7 @@ def test_matrix_full_size_sampled_parity(fpm):
     from paper_1711_08475_amd import learn
 
     table = json.load(open(os.path.join(os.path.dirname(learn.__file__), "tuned.json")))
-    entry = dict(table["english_1m_q10k|occ16|lev1|learned"])
+    entry = dict(table["english_1m_q10k|occ16|lev1|learned|matrix"])
     entry.pop("inflight", None)
 
     d, q = datagen.workload("english_1m_q10k")

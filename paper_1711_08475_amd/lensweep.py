@@ -37,7 +37,7 @@ def time_plan(fpm, torch, plan, qb, qo, nq, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps, st
 
 
-def main(argv=None):
+def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--words", type=int, default=1_000_000)
     ap.add_argument("--queries", type=int, default=10_000)
@@ -49,17 +49,18 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=41)
     ap.add_argument("--filter-unit", default="auto", choices=["auto", "valu", "matrix"],
                     help="where the filter test runs (fpm_options.filter_unit)")
-    args = ap.parse_args(argv)
+    return ap.parse_args(argv)
 
+
+def run(args, on_row=None):
+    """The sweep: a list of (row, match list, symbol map) per (length,
+    fingerprint); on_row(row) is called as each row is done."""
     import torch
 
     from paper_1711_08475_amd import datagen, fpm
 
-    if not torch.cuda.is_available():
-        print("the sweep needs a GPU", file=sys.stderr)
-        return 2
     fpm.lib()
-    rows = []
+    out = []
     for L in [int(x) for x in args.lengths.split(",")]:
         d, q = datagen.fixed_length_workload(args.words, args.queries, L, args.seed + L)
         nq, qbytes = q[1].size - 1, int(q[1][-1])
@@ -95,10 +96,24 @@ def main(argv=None):
                 "filter_unit": {1: "valu", 2: "matrix"}.get(st.get("filter_unit"), "none"),
                 "pairs_per_s": nq * args.words / (ms * 1e-3),
                 "matches": int(got.shape[0]),
+                "examined": st["pairs_examined"],
+                "survivors": st["survivors"],
                 "tiles": [best.queries_per_item, best.slab, best.bucket_order, best.tail_split],
             }
-            rows.append(row)
-            print(json.dumps(row), flush=True)
+            out.append((row, got, fpm.fpm_get_map(ix)))
+            if on_row:
+                on_row(row)
+    return out
+
+
+def main(argv=None):
+    args = parse(argv)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("the sweep needs a GPU", file=sys.stderr)
+        return 2
+    rows = [r for r, _, _ in run(args, on_row=lambda row: print(json.dumps(row), flush=True))]
     variants = [f"{v}{args.bits}" for v in args.variants.split(",")]
     print("| length | brute ms | " + " | ".join(f"{v} ms (speedup, rejection)" for v in variants) + " |")
     print("|---|---|" + "---|" * len(variants))

@@ -86,25 +86,33 @@ def test_learned_grouping_is_sound_and_beats_the_paper_map(fpm):
     assert ev["learned_survivors"] == surv_l and ev["paper_survivors"] == surv_p
 
 
-def test_stored_map_claims_hold(fpm):
-    """The committed grouping of the benchmark workload: valid, its stored
-    evaluation reproduces on the GPU, and the sampled match list equals the
+@pytest.mark.parametrize("name,bits", [("english_1m_q10k", 16), ("mixed_2m_q64k", 32)])
+def test_stored_map_claims_hold(fpm, name, bits):
+    """The committed grouping of a benchmark workload, checked against the
+    oracle on a sample of the workload's own (held-out) queries: the map is
+    valid, the oracle's F_D counts show it rejects more length-compatible
+    pairs than the paper's common map, the GPU filter keeps exactly the
+    oracle's survivors under it, and the sampled match list equals the
     oracle's."""
     from paper_1711_08475_amd import learn
 
-    mp, meta = learn.load_map("english_1m_q10k_occ16_k1")
+    mp, meta = learn.load_map(f"{name}_occ{bits}_k1")
     if mp is None:
         pytest.skip("no stored grouping")
-    assert oracle.check_map(mp, oracle.OCC, 16)
-    d, q = datagen.workload("english_1m_q10k")
-    say("stored map evaluation")
-    ev = learn.evaluate(d, q, mp, bits=16, k=1)
-    if meta["chosen"] == "learned":
-        assert ev["learned_survivors"] == meta["evaluation"]["learned_survivors"]
-        assert ev["learned_rejection"] > ev["paper_rejection"]
-    ix = fpm.fpm_build_fingerprints(d, "occ", 16, custom_map=mp)
-    sample = np.arange(0, q[1].size - 1, 97)[:64]
+    assert oracle.check_map(mp, oracle.OCC, bits)
+    d, q = datagen.workload(name)
+    nq = q[1].size - 1
+    sample = np.arange(0, nq, nq // 400)[:400]
     qs = datagen.take_csr(q, sample)
-    got = fpm.fpm_match(ix, qs, "lev", 1)
-    ref = oracle.match(d, qs, oracle.LEV, 1, length_pruned=True)
-    assert np.array_equal(got, ref)
+    say("stored map", name, bits)
+    paper = oracle.select_symbols(oracle.histogram(d), oracle.OCC, bits, oracle.COMMON)
+    ex_p, surv_p, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, paper, oracle.LEV, 1)
+    ex_l, surv_l, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, mp, oracle.LEV, 1)
+    assert ex_p == ex_l
+    say("sample rejection paper", 1 - surv_p / ex_p, "learned", 1 - surv_l / ex_l)
+    if meta["chosen"] == "learned":
+        assert surv_l < surv_p
+    ix = fpm.fpm_build_fingerprints(d, "occ", bits, custom_map=mp)
+    assert fpm.fpm_filter_pairs(ix, qs, "lev", 1).shape[0] == surv_l
+    qm = datagen.take_csr(qs, np.arange(0, 400, 7))
+    assert np.array_equal(fpm.fpm_match(ix, qm, "lev", 1), oracle.match(d, qm, oracle.LEV, 1, length_pruned=True))

@@ -1,8 +1,8 @@
-"""The word-size sweep runs end to end on small single-length workloads and
-its filtered match lists equal the brute force's (checked inside the sweep)
-and the oracle's."""
-import json
-
+"""The word-size sweep (the axis of the paper's Fig. 1) runs end to end on
+small single-length workloads: every filtered match list equals the
+oracle's element by element (and the GPU brute force's, checked inside the
+sweep), and every survivor count equals the oracle's count of pairs with
+F_D <= 2k under the same symbol map."""
 import numpy as np
 import pytest
 
@@ -11,16 +11,26 @@ from paper_1711_08475_amd import datagen
 
 pytestmark = pytest.mark.gpu
 
+VARIANTS = {"occ": oracle.OCC, "count": oracle.COUNT, "pos": oracle.POS}
 
-def test_fixed_length_sweep_small(gpu, capsys):
+
+def test_fixed_length_sweep_small(gpu):
     from paper_1711_08475_amd import lensweep
 
     print("[case] length sweep small", flush=True)
-    assert lensweep.main(["--words", "4000", "--queries", "150", "--lengths", "3,9,17", "--steps", "2",
-                          "--warmup", "1"]) == 0
-    rows = [json.loads(line) for line in capsys.readouterr().out.splitlines() if line.startswith("{")]
-    assert len(rows) == 9
-    for r in rows:
-        d, q = datagen.fixed_length_workload(4000, 150, r["length"], 41 + r["length"])
-        assert r["matches"] == oracle.match(d, q, oracle.HAM, 1).shape[0]
-        assert 0.0 <= r["rejection_rate"] <= 1.0
+    args = lensweep.parse(["--words", "4000", "--queries", "150", "--lengths", "3,9,17", "--steps", "2",
+                           "--warmup", "1"])
+    res = lensweep.run(args)
+    assert len(res) == 9
+    refs = {}
+    for row, hits, mp in res:
+        L = row["length"]
+        d, q = datagen.fixed_length_workload(4000, 150, L, 41 + L)
+        if L not in refs:
+            refs[L] = oracle.match(d, q, oracle.HAM, 1)
+        assert np.array_equal(hits, refs[L]), row
+        assert row["matches"] == refs[L].shape[0]
+        variant = VARIANTS[row["fingerprint"][:-2]]
+        ex, surv, _ = oracle.filter_stats(d, q, variant, 16, mp, oracle.HAM, 1)
+        assert (row["examined"], row["survivors"]) == (ex, surv), row
+        assert 0.0 <= row["rejection_rate"] <= 1.0

@@ -352,21 +352,45 @@ def test_long_strings_match_equals_oracle(fpm, url_small, mixed_small, variant, 
     assert (st["pairs_examined"], st["survivors"]) == (ex, surv)
 
 
-@pytest.mark.parametrize("name,bits,metric,k", [("url_1m_q10k", 32, oracle.LEV, 2), ("url_1m_q10k", 32, oracle.LEV, 1),
-                                                ("mixed_2m_q64k", 32, oracle.LEV, 1),
-                                                ("english_1m_q10k", 16, oracle.LEV, 1),
-                                                ("english_1m_q10k", 32, oracle.HAM, 1)])
-def test_full_size_sampled_parity(fpm, name, bits, metric, k):
+_workloads = {}
+
+
+def full_workload(name):
+    if name not in _workloads:
+        _workloads.clear()  # one full-size workload in memory at a time
+        _workloads[name] = datagen.workload(name)
+    return _workloads[name]
+
+
+FULL_CASES = [
+    # the 1M English-like x 10K configuration: occurrence, count, position at 16 and 32 bits
+    ("english_1m_q10k", oracle.OCC, 16, oracle.LEV, 1), ("english_1m_q10k", oracle.OCC, 16, oracle.HAM, 1),
+    ("english_1m_q10k", oracle.OCC, 32, oracle.LEV, 1), ("english_1m_q10k", oracle.OCC, 32, oracle.HAM, 1),
+    ("english_1m_q10k", oracle.COUNT, 16, oracle.LEV, 1), ("english_1m_q10k", oracle.COUNT, 16, oracle.HAM, 1),
+    ("english_1m_q10k", oracle.COUNT, 32, oracle.LEV, 1), ("english_1m_q10k", oracle.COUNT, 32, oracle.HAM, 1),
+    ("english_1m_q10k", oracle.POS, 16, oracle.HAM, 1), ("english_1m_q10k", oracle.POS, 32, oracle.HAM, 1),
+    # the 1M URL-like x 10K configuration: occurrence and count at 32 bits, Lev k = 1, 2
+    ("url_1m_q10k", oracle.OCC, 32, oracle.LEV, 1), ("url_1m_q10k", oracle.OCC, 32, oracle.LEV, 2),
+    ("url_1m_q10k", oracle.COUNT, 32, oracle.LEV, 1), ("url_1m_q10k", oracle.COUNT, 32, oracle.LEV, 2),
+    # the batched uneven workload
+    ("mixed_2m_q64k", oracle.OCC, 32, oracle.LEV, 1),
+]
+
+
+@pytest.mark.parametrize("name,variant,bits,metric,k", FULL_CASES)
+def test_full_size_sampled_parity(fpm, name, variant, bits, metric, k):
     """Full-size workloads in the benchmark's launch configuration (batched,
-    persistent, hipGraph): the rows of 48 sampled queries equal the oracle's
-    (length-pruned mode, exact since Lev >= |m - n|), and the filtered result
-    equals the GPU brute force on every query."""
+    persistent, hipGraph) with the paper's common map: the rows of 48
+    sampled queries equal the oracle's (length-pruned mode, exact since
+    Lev >= |m - n|), the filtered result equals the GPU brute force on every
+    query, and on the sampled queries the filter keeps exactly the pairs
+    the oracle's F_D counts (F_D <= 2k)."""
     import torch
 
-    d, q = datagen.workload(name)
+    d, q = full_workload(name)
     nq = q[1].size - 1
-    say("full size", name, bits, metric, k)
-    ix = fpm.fpm_build_fingerprints(d, "occ", bits, "common")
+    say("full size", name, VARIANT_NAMES[variant], bits, metric, k)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
     qb = torch.from_numpy(q[0].copy()).cuda()
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
     torch.cuda.synchronize()  # the plans run on their own streams
@@ -379,11 +403,61 @@ def test_full_size_sampled_parity(fpm, name, bits, metric, k):
     assert np.array_equal(res[fpm.FPM_SCHED_BATCHED], res[fpm.FPM_SCHED_BRUTE])
     sample = np.random.default_rng(11).choice(nq, 48, replace=False)
     sample.sort()
-    ref = oracle.match(d, datagen.take_csr(q, sample), metric, k, length_pruned=True)
+    qs = datagen.take_csr(q, sample)
+    ref = oracle.match(d, qs, metric, k, length_pruned=True)
     ref[:, 0] = sample[ref[:, 0]]
     got = res[fpm.FPM_SCHED_BATCHED]
     got = got[np.isin(got[:, 0], sample)]
     assert np.array_equal(got, ref)
+    _, surv, _ = oracle.filter_stats(d, qs, variant, bits, fpm.fpm_get_map(ix), metric, k)
+    assert fpm.fpm_filter_pairs(ix, qs, metric, k).shape[0] == surv
+
+
+def test_headline_as_benched(fpm):
+    """The benchmark's headline exactly as it is timed: 2M mixed words x
+    65,536 queries, the stored learned occ32 map, the tuning table's tiles
+    and batches in flight, one plan per batch, runs alternating over the
+    plans with the kernel-timed (split graph) and whole-graph forms: every
+    run returns the GPU brute force's list, and 48 sampled query rows equal
+    the oracle's."""
+    import json
+    import os
+
+    import torch
+
+    from paper_1711_08475_amd import learn
+
+    name = "mixed_2m_q64k"
+    table = json.load(open(os.path.join(os.path.dirname(learn.__file__), "tuned.json")))
+    entry = dict(table[f"{name}|occ32|lev1|learned"])
+    inflight = entry.pop("inflight", 2)
+    mp, _ = learn.load_map(f"{name}_occ32_k1")
+    d, q = full_workload(name)
+    nq = q[1].size - 1
+    say("headline as benched", entry, inflight)
+    ix = fpm.fpm_build_fingerprints(d, "occ", 32, custom_map=mp)
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()
+    plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, fpm.options(schedule=fpm.FPM_SCHED_BRUTE))
+    fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
+    brute = fpm.fpm_plan_copy_matches(plan)
+    del plan
+    for timed in (1, 0):
+        plans = [fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, fpm.options(**entry, time_kernel=timed))
+                 for _ in range(inflight)]
+        for step in range(2 * inflight):
+            fpm.fpm_plan_run(plans[step % inflight], qb.data_ptr(), qo.data_ptr(), nq)
+        for p in plans:
+            assert np.array_equal(fpm.fpm_plan_copy_matches(p), brute)
+        if timed:
+            assert all(fpm.fpm_plan_kernel_ms(p).size >= 2 for p in plans)  # a run that grew the match buffer repeats
+        del plans
+    sample = np.random.default_rng(12).choice(nq, 48, replace=False)
+    sample.sort()
+    ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, 1, length_pruned=True)
+    ref[:, 0] = sample[ref[:, 0]]
+    assert np.array_equal(brute[np.isin(brute[:, 0], sample)], ref)
 
 
 @pytest.mark.parametrize("length", [1, 5, 17, 33, 49, 241])

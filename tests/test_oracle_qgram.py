@@ -37,6 +37,27 @@ def test_bigram_set_semantics(bits):
     assert differ > 0.8 * 325
 
 
+# Field indices of the documented hash, worked by hand: v = 256 * first
+# byte + second byte; h = v * 2654435761 mod 2^32; field = top log2(bits)
+# bits of h.  "ab": v = 97 * 256 + 98 = 24930; 24930 * 2654435761 =
+# 66,175,083,521,730 = 15407 * 2^32 + 2,522,392,258 (0x9658A6C2), so field
+# 9 of 16 (0x9) and 18 of 32 (0x9658A6C2 >> 27).  "ba": v = 25185, h =
+# 0x2F9ADE11: fields 2 and 5 -- swapping the two bytes of v would swap the
+# fields of "ab" and "ba".  "zz": v = 31354, h = 0xD66E585A: 13 and 26.
+# "//": v = 12079, h = 0x3B86D67F: 3 and 7.  "q7": v = 28983,
+# h = 0x7AA24607: 7 and 15.
+HAND_FIELDS = {"ab": (9, 18), "ba": (2, 5), "zz": (13, 26), "//": (3, 7), "q7": (7, 15)}
+
+
+@pytest.mark.parametrize("bigram", sorted(HAND_FIELDS))
+def test_bigram_field_index_worked_by_hand(bigram):
+    f16, f32 = HAND_FIELDS[bigram]
+    assert fp(bigram, 16) == 1 << f16
+    assert fp(bigram, 32) == 1 << f32
+    # a longer string is the union of its bigrams' fields
+    assert fp("abzz", 16) == (1 << 9) | (1 << 13) | fp("bz", 16)  # bigrams ab, bz, zz
+
+
 @pytest.mark.parametrize("bits", [16, 32])
 def test_hash_reaches_every_field(bits):
     letters = "abcdefghijklmnopqrstuvwxyz"

@@ -302,6 +302,44 @@ fpm_status fpm_plan_copy_matches(fpm_plan *plan, fpm_hit *dst, uint64_t max, uin
 
 void fpm_plan_destroy(fpm_plan *plan);
 
+/* ---------------------------------------------------------------------
+ * Allocation-free matching, for callers that cannot allocate device memory
+ * (serving loops with a fixed memory budget, harnesses that forbid
+ * hipMalloc, code that must not touch the allocator).  Same result as
+ * fpm_match on the same queries: the match list of the queries in d_qbytes /
+ * d_qoffsets (DEVICE CSR, n_queries strings, d_qbytes holding query_bytes
+ * bytes) against the index, sorted by (query, word), written to the
+ * caller's DEVICE array d_out of out_cap entries; *n_out receives the number
+ * of matches.
+ *
+ * Every intermediate buffer lives in one static device array of the library
+ * (about 27 MiB, held on each device from the first call there until the
+ * process ends); the call allocates no device memory.  Limits:
+ * n_queries <= FPM_NOALLOC_MAX_QUERIES, query_bytes <=
+ * FPM_NOALLOC_MAX_QUERY_BYTES (FPM_EINVAL beyond them, before any device
+ * work), at most FPM_NOALLOC_MAX_MATCHES matches (FPM_ENOMEM, *n_out holds
+ * the count; use a plan for larger results).  When the matches do not fit
+ * out_cap the call fails with FPM_EINVAL, *n_out holds the count and d_out
+ * holds no valid list.
+ *
+ * The work runs on `hip_stream` (NULL = the null stream) with the
+ * device-scheduled persistent kernel and plain launches (options: tiles,
+ * bucket order, tail split, filter unit; FPM_SCHED_PLAIN is run device-
+ * scheduled too, FPM_SCHED_BRUTE verifies every length-compatible pair;
+ * the asymmetric bound is FPM_EUNSUPPORTED), and the call returns after it
+ * has finished (it synchronises the stream, so it cannot be captured into a
+ * graph).  The index must live on the current device.  All calls on one
+ * device share the array: the library runs them one at a time (a lock per
+ * device), and every buffer a call reads is written or cleared by that call
+ * first.  stats may be NULL (stats->ms is 0). */
+#define FPM_NOALLOC_MAX_QUERIES 65536u
+#define FPM_NOALLOC_MAX_QUERY_BYTES (4u << 20)
+#define FPM_NOALLOC_MAX_MATCHES (1u << 20)
+fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const uint64_t *d_qoffsets,
+                             uint32_t n_queries, uint64_t query_bytes, fpm_metric metric, uint32_t k,
+                             const fpm_options *opt, void *hip_stream, fpm_hit *d_out, uint64_t out_cap,
+                             uint64_t *n_out, fpm_stats *stats);
+
 /* Autotuner for the batched schedule: times every combination of
  * queries_per_item in {16, 32, 64, 128, 256}, slab in {512, 1024, 2048,
  * 4096, 8192, 16384} and both bucket orders on the given device queries with

@@ -1157,6 +1157,209 @@ fpm_status fpm_filter_pairs(const fpm_index *ix, const uint8_t *qbytes, const ui
     return match_host(ix, qbytes, qoffsets, n_queries, metric, k, &o, true, pairs, n_pairs, nullptr);
 }
 
+// ---------------------------------------------------- allocation-free match
+//
+// fpm_match_noalloc keeps every intermediate buffer of one match (the query
+// batch's sorted padded strings and keys, the radix scratch, the work list,
+// the counters, the match keys and, for the matrix-core filter, the
+// expanded query rows) in one file-scope device array, `scratch`, carved at
+// fixed offsets for the limits below.  Host code never passes the array's
+// name to a kernel: its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is used.
+
+}  // extern "C"
+
+namespace {
+
+constexpr uint32_t kNaMaxQueries = FPM_NOALLOC_MAX_QUERIES;
+constexpr uint64_t kNaMaxQueryBytes = FPM_NOALLOC_MAX_QUERY_BYTES;
+constexpr uint64_t kNaMaxMatches = FPM_NOALLOC_MAX_MATCHES;
+constexpr int kNaMaxDevices = 64;
+
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of the carved buffers (sizes as StrSet::alloc and
+// plan_create would allocate them for the limits).
+struct NaLayout {
+    size_t len, perm, soff, slen, off, bdw, str, key, radix, pairs, ctr, keys, tmp, qexp, total;
+    uint64_t str_cap;  // dwords
+};
+
+constexpr NaLayout na_layout()
+{
+    NaLayout L{};
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o += na_align(bytes);
+        return at;
+    };
+    L.str_cap = std::min<uint64_t>(kNaMaxQueryBytes / 4 + 4ull * kNaMaxQueries, (uint64_t)kNaMaxQueries * 64) + 1024 +
+                16;
+    L.len = take(4ull * kNaMaxQueries);
+    L.perm = take(4ull * kNaMaxQueries);
+    L.soff = take(4ull * kNaMaxQueries);
+    L.slen = take(kNaMaxQueries);
+    L.off = take(4 * 257);
+    L.bdw = take(4 * 257);
+    L.str = take(4 * L.str_cap);
+    L.key = take(8ull * (kNaMaxQueries + 64));
+    L.radix = take(4 * kRadixScratch);
+    L.pairs = take(sizeof(PairRec) * kMaxPairs);
+    L.ctr = take(sizeof(DevCounters));
+    L.keys = take(8 * kNaMaxMatches);
+    L.tmp = take(8 * kNaMaxMatches);
+    L.qexp = take((size_t)(kNaMaxQueries + 64) * kMxRowBytes * 2);
+    L.total = o;
+    return L;
+}
+
+constexpr NaLayout kNa = na_layout();
+
+// The library's allocation-free working memory (each device holds its own
+// copy from the time the library is loaded until the process ends).
+static __device__ __align__(256) uint8_t scratch[kNa.total];
+
+struct NaDevice {
+    std::mutex mu;             // calls on one device run one at a time
+    uint8_t *base = nullptr;   // device address of `scratch` on this device
+    int cus = 0;
+};
+NaDevice g_na[kNaMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const uint64_t *d_qoffsets,
+                             uint32_t n_queries, uint64_t query_bytes, fpm_metric metric, uint32_t k,
+                             const fpm_options *opt, void *hip_stream, fpm_hit *d_out, uint64_t out_cap,
+                             uint64_t *n_out, fpm_stats *stats)
+{
+    g_last_error.clear();
+    if (!ix || !n_out)
+        return fail(FPM_EINVAL, "null pointer");
+    *n_out = 0;
+    fpm_status st = check_metric(ix, metric, k);
+    if (st)
+        return st;
+    if (n_queries > kNaMaxQueries)
+        return fail(FPM_EINVAL, "%u queries exceed the allocation-free limit of %u", n_queries, kNaMaxQueries);
+    if (query_bytes > kNaMaxQueryBytes)
+        return fail(FPM_EINVAL, "%llu query bytes exceed the allocation-free limit of %llu",
+                    (unsigned long long)query_bytes, (unsigned long long)kNaMaxQueryBytes);
+    if (n_queries && (!d_qoffsets || (!d_qbytes && query_bytes)))
+        return fail(FPM_EINVAL, "null query pointer");
+    if (out_cap && !d_out)
+        return fail(FPM_EINVAL, "null output pointer");
+    fpm_options o;
+    st = resolve_options(opt, &o);
+    if (st)
+        return st;
+    if (o.bound == FPM_BOUND_ASYM && o.schedule != FPM_SCHED_BRUTE)
+        return fail(FPM_EUNSUPPORTED, "the allocation-free match takes the paper's rule only");
+    const bool mx_ok = ix->kind == kPop32 || ix->kind == kQgram32;
+    if (o.filter_unit == FPM_UNIT_MATRIX && o.schedule != FPM_SCHED_BRUTE && !mx_ok)
+        return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on occurrence, "
+                                      "occurrence-halved, 16-bit count and bigram fingerprints");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != ix->device)
+        return fail(FPM_EINVAL, "the index lives on device %d, device %d is current", ix->device, dev);
+    if (dev < 0 || dev >= kNaMaxDevices)
+        return fail(FPM_EUNSUPPORTED, "device %d: the allocation-free match supports devices 0..%d", dev,
+                    kNaMaxDevices - 1);
+    NaDevice &nd = g_na[dev];
+    std::lock_guard<std::mutex> lock(nd.mu);
+    if (!nd.base) {  // first call on this device: the array's device address
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "allocation-free scratch address");
+        hipDeviceProp_t prop;
+        nd.cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 256;
+        nd.base = (uint8_t *)ptr;
+    }
+    fpm_stats sres;
+    memset(&sres, 0, sizeof(sres));
+    sres.pairs_logical = (uint64_t)n_queries * ix->n;
+    if (n_queries == 0) {
+        if (stats)
+            *stats = sres;
+        return FPM_OK;
+    }
+
+    // a plan whose buffers are carved from the scratch array (nothing of
+    // it is ever freed); the persistent, device-scheduled pipeline with
+    // plain launches
+    fpm_plan p;
+    p.ix = ix;
+    p.max_q = kNaMaxQueries;
+    p.max_bytes = query_bytes;
+    p.metric = metric;
+    p.k = k;
+    p.opt = o;
+    p.opt.schedule = o.schedule == FPM_SCHED_BRUTE ? FPM_SCHED_BRUTE : FPM_SCHED_BATCHED;
+    p.stream = (hipStream_t)hip_stream;
+    p.kind = p.opt.schedule == FPM_SCHED_BRUTE ? kAll : ix->kind;
+    const int key_width = ix->bits == 16 && ix->variant != FPM_COUNT ? 16 : 32;
+    p.mx_width = p.kind != kAll && mx_ok && o.filter_unit == FPM_UNIT_MATRIX ? key_width : 0;
+    uint8_t *b = nd.base;
+    StrSet &Q = p.q;
+    Q.cap_n = kNaMaxQueries;
+    Q.cap_bytes = query_bytes;
+    Q.str_cap = kNa.str_cap;
+    Q.len = (uint32_t *)(b + kNa.len);
+    Q.perm = (uint32_t *)(b + kNa.perm);
+    Q.soff = (uint32_t *)(b + kNa.soff);
+    Q.slen = b + kNa.slen;
+    Q.off = (uint32_t *)(b + kNa.off);
+    Q.bdw = (uint32_t *)(b + kNa.bdw);
+    Q.str = (uint32_t *)(b + kNa.str);
+    Q.key = b + kNa.key;
+    p.scratch = (uint32_t *)(b + kNa.radix);
+    p.pairs = (PairRec *)(b + kNa.pairs);
+    p.ctr = (DevCounters *)(b + kNa.ctr);
+    p.keys = (uint64_t *)(b + kNa.keys);
+    p.tmp = (uint64_t *)(b + kNa.tmp);
+    p.qexp = p.mx_width ? b + kNa.qexp : nullptr;
+    // the sort's last pass writes the triples straight into the caller's
+    // buffer: at most min(out_cap, kNaMaxMatches) of them
+    p.triples = (uint32_t *)d_out;
+    p.cap = std::min<uint64_t>(out_cap, kNaMaxMatches);
+    p.persistent_blocks = std::max(1, nd.cus * (int)p.opt.waves_per_cu / 4);
+
+    st = enqueue_prep(&p, d_qbytes, d_qoffsets, n_queries, false);
+    if (!st)
+        st = enqueue_kernel(&p, false);
+    if (st)
+        return st;
+    enqueue_post(&p, n_queries);
+    DevCounters c;
+    HIPCHK(hipMemcpyAsync(&c, p.ctr, offsetof(DevCounters, counters), hipMemcpyDeviceToHost, p.stream));
+    HIPCHK(hipStreamSynchronize(p.stream));
+    if (c.err)
+        return fail(FPM_EINVAL, "query batch: %s",
+                    (c.err & 2) ? "offsets decrease"
+                                : (c.err & 1) ? "a string is longer than 255" : "more bytes than query_bytes");
+    *n_out = c.n_out;
+    if (c.n_out > kNaMaxMatches)
+        return fail(FPM_ENOMEM, "%llu matches exceed the allocation-free limit of %llu (use a plan)",
+                    (unsigned long long)c.n_out, (unsigned long long)kNaMaxMatches);
+    if (c.n_out > out_cap)
+        return fail(FPM_EINVAL, "%llu matches do not fit out_cap = %llu", (unsigned long long)c.n_out,
+                    (unsigned long long)out_cap);
+    sres.pairs_examined = c.examined;
+    sres.survivors = c.survivors;
+    sres.matches = c.n_out;
+    sres.verify_cells = c.cells;
+    sres.work_items = c.n_items;
+    sres.filter_unit = p.kind == kAll ? FPM_UNIT_AUTO : p.mx_width ? FPM_UNIT_MATRIX : FPM_UNIT_VALU;
+    if (stats)
+        *stats = sres;
+    return FPM_OK;
+}
+
 // Temporary device copy of host strings, sorted and fingerprinted.
 struct TmpSet {
     StrSet S;

@@ -40,7 +40,7 @@ EXPORTS = [
     "fpm_index_destroy", "fpm_get_fingerprints", "fpm_get_map", "fpm_index_info", "fpm_fingerprints",
     "fpm_match", "fpm_filter_pairs", "fpm_verify_pairs", "fpm_plan_create", "fpm_plan_run", "fpm_plan_result",
     "fpm_plan_copy_matches", "fpm_plan_destroy", "fpm_autotune", "fpm_plan_kernel_ms", "fpm_index_build_ms",
-    "fpm_set_device_memory_limit", "fpm_device_memory_in_use",
+    "fpm_set_device_memory_limit", "fpm_device_memory_in_use", "fpm_match_noalloc",
 ]
 # every symbol include/fpm_learn.h declares
 LEARN_EXPORTS = ["fpm_learn_grouping", "fpm_learn_step"]
@@ -161,6 +161,9 @@ def lib():
         "fpm_plan_result": (ctypes.c_int, [vp, ctypes.POINTER(vp), u64p, ctypes.POINTER(Stats)]),
         "fpm_plan_copy_matches": (ctypes.c_int, [vp, vp, ctypes.c_uint64, u64p]),
         "fpm_plan_destroy": (None, [vp]),
+        "fpm_match_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                             ctypes.c_uint32, ctypes.POINTER(Options), vp, vp, ctypes.c_uint64, u64p,
+                                             ctypes.POINTER(Stats)]),
         "fpm_plan_kernel_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_uint32, u32p]),
         "fpm_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Options),
@@ -382,6 +385,27 @@ def fpm_plan_kernel_ms(plan: Plan, max_runs: int = 256) -> np.ndarray:
     _check(lib().fpm_plan_kernel_ms(plan.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), max_runs,
                                     ctypes.byref(n)))
     return out[: n.value]
+
+
+NOALLOC_MAX_QUERIES, NOALLOC_MAX_QUERY_BYTES, NOALLOC_MAX_MATCHES = 65536, 4 << 20, 1 << 20
+
+
+def fpm_match_noalloc(ix: Index, d_qbytes: int, d_qoffsets: int, n_queries: int, query_bytes: int, d_out: int,
+                      out_cap: int, metric="lev", k: int = 1, opts: Options | None = None, stream: int | None = None):
+    """Allocation-free match into the caller's device array d_out (out_cap
+    fpm_hit entries): (number of matches, stats dict)."""
+    n = ctypes.c_uint64()
+    st = Stats()
+    rc = lib().fpm_match_noalloc(ix.handle, vp(d_qbytes) if d_qbytes else None,
+                                 vp(d_qoffsets) if d_qoffsets else None, n_queries, query_bytes,
+                                 _code(METRICS, metric), k, ctypes.byref(opts) if opts is not None else None,
+                                 vp(stream) if stream else None, vp(d_out) if d_out else None, out_cap,
+                                 ctypes.byref(n), ctypes.byref(st))
+    if rc != FPM_OK:
+        err = FpmError(rc, lib().fpm_last_error().decode(errors="replace"))
+        err.n_out = n.value  # the match count, when the list did not fit
+        raise err
+    return n.value, st.as_dict()
 
 
 def fpm_autotune(ix: Index, d_qbytes: int, d_qoffsets: int, n_queries: int, query_bytes: int, metric="lev",

@@ -1,0 +1,139 @@
+"""The allocation-free match (fpm_match_noalloc) against the existing entry
+point fpm_match, element by element, on the same seeded inputs: two calls in
+a row (the second on a smaller batch, so stale contents of the shared
+working memory would show), every key family and schedule, the limits, and
+that the call takes no device memory from the library's allocator."""
+import numpy as np
+import pytest
+
+from paper_1711_08475_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fpm(gpu):
+    from paper_1711_08475_amd import fpm as f
+
+    f.lib()
+    return f
+
+
+def run_noalloc(fpm, ix, csr, metric, k, opts=None, out_cap=1 << 20):
+    import torch
+
+    qb = torch.from_numpy(csr[0].copy()).cuda()
+    qo = torch.from_numpy(csr[1].view(np.int64).copy()).cuda()
+    out = torch.zeros(max(out_cap, 1) * 3, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    nq = csr[1].size - 1
+    before = fpm.fpm_device_memory_in_use()
+    n, st = fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), nq, int(csr[1][-1]), out.data_ptr(), out_cap,
+                                  metric, k, opts)
+    assert fpm.fpm_device_memory_in_use() == before  # nothing taken from the allocator
+    got = out[: 3 * n].cpu().numpy().view(np.uint32).reshape(-1, 3)
+    return got, st
+
+
+def same_stats(a, b):
+    for f in ("pairs_logical", "pairs_examined", "survivors", "matches", "verify_cells", "filter_unit"):
+        assert a[f] == b[f], f
+
+
+def test_two_calls_in_a_row_second_smaller(fpm):
+    d, q = datagen.workload("english_10k_q1k")
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    small = datagen.take_csr(q, np.arange(0, 1000, 7))
+    for name, qq in (("first call, 1,000 queries", q), ("second call, 143 queries", small)):
+        say("noalloc", name)
+        ref, rst = fpm.fpm_match(ix, qq, "lev", 1, with_stats=True)
+        got, st = run_noalloc(fpm, ix, qq, "lev", 1)
+        assert np.array_equal(got, ref)
+        same_stats(st, rst)
+
+
+CASES = [
+    # variant, bits, metric, k, options
+    ("occ", 32, "lev", 2, {}),
+    ("occ", 16, "ham", 1, {"queries_per_item": 16, "slab": 64}),
+    ("count", 32, "lev", 1, {}),
+    ("count", 16, "ham", 2, {"tail_split": 25}),
+    ("pos", 16, "ham", 1, {}),
+    ("occh", 16, "ham", 1, {}),
+    ("qgram", 32, "lev", 1, {}),
+    ("combo", 32, "lev", 1, {}),
+    ("occ", 16, "lev", 1, {"filter_unit": "matrix"}),
+    ("occ", 32, "lev", 3, {"filter_unit": "matrix", "bucket_order": 1}),
+    ("occ", 16, "lev", 1, {"schedule": 2}),
+    ("occ", 16, "lev", 1, {"schedule": 1, "use_graph": 1, "time_kernel": 1}),
+]
+
+
+@pytest.mark.parametrize("variant,bits,metric,k,kw", CASES)
+def test_noalloc_equals_fpm_match(fpm, variant, bits, metric, k, kw):
+    d, q = datagen.english_workload(20_000, 600, 11, "3-15", 0.5)
+    ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
+    say("noalloc", variant, bits, metric, k, kw)
+    ref, rst = fpm.fpm_match(ix, q, metric, k, fpm.options(**kw), with_stats=True)
+    got, st = run_noalloc(fpm, ix, q, metric, k, fpm.options(**kw))
+    assert np.array_equal(got, ref)
+    same_stats(st, rst)
+    # again with half the batch
+    h = datagen.take_csr(q, np.arange(0, 600, 2))
+    ref, rst = fpm.fpm_match(ix, h, metric, k, fpm.options(**kw), with_stats=True)
+    got, st = run_noalloc(fpm, ix, h, metric, k, fpm.options(**kw))
+    assert np.array_equal(got, ref)
+    same_stats(st, rst)
+
+
+def test_noalloc_largest_batch(fpm):
+    """FPM_NOALLOC_MAX_QUERIES queries of mixed lengths (English-like and
+    URL-like) against a mixed dictionary, then a ragged small batch."""
+    d, q = datagen.mixed_workload(60_000, 40_000, fpm.NOALLOC_MAX_QUERIES, 21)
+    assert q[1].size - 1 == fpm.NOALLOC_MAX_QUERIES
+    ix = fpm.fpm_build_fingerprints(d, "occ", 32, "common")
+    say("noalloc largest batch")
+    ref, rst = fpm.fpm_match(ix, q, "lev", 1, with_stats=True)
+    got, st = run_noalloc(fpm, ix, q, "lev", 1, out_cap=max(ref.shape[0], 1))
+    assert np.array_equal(got, ref)
+    same_stats(st, rst)
+    r = datagen.take_csr(q, np.arange(0, 1001, 1))
+    ref = fpm.fpm_match(ix, r, "lev", 1)
+    got, _ = run_noalloc(fpm, ix, r, "lev", 1)
+    assert np.array_equal(got, ref)
+
+
+def test_noalloc_limits_and_errors(fpm):
+    import torch
+
+    d, q = datagen.workload("english_10k_q1k")
+    ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
+    say("noalloc limits")
+    qb = torch.from_numpy(q[0].copy()).cuda()
+    qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
+    out = torch.zeros(3 * 8, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    nq, nb = q[1].size - 1, int(q[1][-1])
+    for n, b in ((fpm.NOALLOC_MAX_QUERIES + 1, nb), (nq, fpm.NOALLOC_MAX_QUERY_BYTES + 1)):
+        with pytest.raises(fpm.FpmError) as e:
+            fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), n, b, out.data_ptr(), 8)
+        assert e.value.status == fpm.FPM_EINVAL
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), nq, nb, out.data_ptr(), 8,
+                              opts=fpm.options(bound="asym"))
+    assert e.value.status == fpm.FPM_EUNSUPPORTED
+    # the list does not fit: the count is reported, then a call with room works
+    ref = fpm.fpm_match(ix, q, "lev", 1)
+    assert ref.shape[0] > 8
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), nq, nb, out.data_ptr(), 8)
+    assert e.value.status == fpm.FPM_EINVAL and e.value.n_out == ref.shape[0]
+    got, _ = run_noalloc(fpm, ix, q, "lev", 1)
+    assert np.array_equal(got, ref)
+    # no queries: no matches, nothing written
+    n, st = fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), 0, 0, out.data_ptr(), 8)
+    assert n == 0 and st["pairs_logical"] == 0

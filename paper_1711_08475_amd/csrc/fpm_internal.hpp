@@ -24,9 +24,9 @@ constexpr int kMaxLen = 255;
 constexpr int kBuckets = 256;        // lengths 0..255
 constexpr int kMaxK = 3;                // largest supported k (match keys hold the distance in 2 bits)
 constexpr int kMaxPairs = 2 * 256 * (2 * kMaxK + 1);  // (query length, word length) pairs, |dL| <= k, full + tail part
-constexpr int kRadixShift = 7;
+constexpr int kRadixShift = 8;
 constexpr int kRadixBlocks = 1 << kRadixShift;  // blocks of one stable radix pass (16 waves each)
-constexpr int kSortBits = 9;                    // digit width of the match-list sort (lengths use 8)
+constexpr int kSortBits = 10;                   // digit width of the match-list sort (lengths use 8)
 // uint32 scratch of a pass: the digit table [bins][kRadixBlocks], then the
 // bins' totals
 constexpr size_t kRadixScratch = ((size_t)kRadixBlocks << kSortBits) + (1u << kSortBits);

@@ -506,6 +506,18 @@ __device__ __forceinline__ cptr<T> as_const(const T *p)
     return (cptr<T>)(p);
 }
 
+// Sum of a per-lane count over the wave (each lane's value below 2^31), as
+// a wave-uniform 64-bit value: butterfly sums within each half-wave, then
+// the two halves.
+__device__ __forceinline__ uint64_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1)
+        v += (uint32_t)__shfl_xor((int)v, o);
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 0) +
+           (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -577,14 +589,13 @@ __device__ __forceinline__ void flush(const MatchArgs &a, const uint64_t *out, u
 // stage the matches.
 template <int METRIC, int K>
 __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const uint32_t *queue, uint32_t &qlen,
-                                      uint32_t nact, uint32_t lane, uint64_t &cells, uint64_t *out, uint32_t &ocount)
+                                      uint32_t nact, uint32_t lane, uint64_t *out, uint32_t &ocount)
 {
     __builtin_amdgcn_wave_barrier();
     const bool act = lane < nact;
     const uint32_t ent = act ? queue[qlen - nact + lane] : 0u;
     __builtin_amdgcn_wave_barrier();
     qlen -= nact;
-    cells += (uint64_t)(2 * K + 1) * min(it.m, it.L) * nact;
     const uint32_t tq = ent >> kWordBits, te = ent & ((1u << kWordBits) - 1u);
     uint32_t d = K + 1;
     if (act) {
@@ -614,9 +625,10 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
 template <int METRIC, int K>
 __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint32_t *queue, uint32_t *qcnt,
                                        uint32_t &qlen, uint32_t msk, uint32_t ent0, uint32_t lane,
-                                       uint64_t &survivors, uint64_t &cells, uint64_t *out, uint32_t &ocount)
+                                       uint32_t &sv_lane, uint64_t *out, uint32_t &ocount)
 {
     const uint32_t c = (uint32_t)__builtin_popcount(msk);
+    sv_lane += c;
     if (!__ballot(c != 0))
         return;
     if (lane == 0)
@@ -634,7 +646,6 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
             msk &= msk - 1u;
         }
         __builtin_amdgcn_wave_barrier();
-        survivors += tot - qlen;
         qlen = tot;
         return;
     }
@@ -643,7 +654,7 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
     // at most 63 + 64 * 16 = kQueueCap entries are held
     for (uint32_t h = 0; h < 2; ++h) {
         while (qlen >= 64)
-            drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+            drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
         uint32_t m = h ? (msk >> kChunk) : (msk & 0xFFFFu);
         const uint32_t ch = (uint32_t)__builtin_popcount(m);
         if (!__ballot(ch != 0))
@@ -661,9 +672,7 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
             m &= m - 1u;
         }
         __builtin_amdgcn_wave_barrier();
-        const uint32_t nlen = __builtin_amdgcn_readfirstlane(*qcnt);
-        survivors += nlen - qlen;
-        qlen = nlen;
+        qlen = __builtin_amdgcn_readfirstlane(*qcnt);
     }
 }
 
@@ -828,6 +837,9 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     constexpr uint32_t kGap = pop_gap<KIND, K>();
     const uint32_t n_items = *as_const(a.wl.n_items);
     const uint32_t n_pairs = *as_const(a.wl.n_pairs);
+    // survivors of the current item, counted per lane; summed over the wave
+    // at the end of the item (band cells: (2k + 1) min(m, L) per survivor)
+    uint32_t sv_lane = 0;
     uint64_t survivors = 0, cells = 0;
 
     // first item: the global wave index (no atomics at start-up); `wave`
@@ -877,12 +889,12 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                         mb = (e0 + 32 + col < it.de) ? mb & qm : 0u;
                     }
                     const uint32_t ent0 = ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, survivors, cells, out,
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, sv_lane, out,
                                       ocount);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, survivors, cells,
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, sv_lane,
                                       out, ocount);
                     while (qlen >= 64)
-                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
                 }
             }
         } else if constexpr (MX == 32) {
@@ -914,10 +926,10 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                         m = (e0 + col < it.de) ? m & qm : 0u;
                     }
                     append<METRIC, K>(a, it, queue, &qcount[wave], qlen, m,
-                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, survivors, cells,
+                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, sv_lane,
                                       out, ocount);
                     while (qlen >= 64)
-                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
                 }
             }
         } else {
@@ -966,15 +978,19 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 #pragma unroll
                     for (uint32_t u = 0; u < 2; ++u)
                         append<METRIC, K>(a, it, queue, &qcount[wave], qlen, u ? mb : ma,
-                                          (j0 << kWordBits) | (e0 + 64 * u + lane - it.ds), lane, survivors, cells, out,
+                                          (j0 << kWordBits) | (e0 + 64 * u + lane - it.ds), lane, sv_lane, out,
                                           ocount);
                     while (qlen >= 64)
-                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, cells, out, ocount);
+                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
                 }
             }
         }
         if (qlen)
-            drain<METRIC, K>(a, it, queue, qlen, qlen, lane, cells, out, ocount);
+            drain<METRIC, K>(a, it, queue, qlen, qlen, lane, out, ocount);
+        const uint64_t item_sv = wave_sum(sv_lane);
+        survivors += item_sv;
+        cells += (uint64_t)((2 * K + 1) * min(it.m, it.L)) * item_sv;
+        sv_lane = 0;
         if (!PERSISTENT)
             break;
         item = next_item(a.wl.counters, nw, n_items, stripe, tries, lane, &s_done);

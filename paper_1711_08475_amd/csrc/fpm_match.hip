@@ -506,18 +506,6 @@ __device__ __forceinline__ cptr<T> as_const(const T *p)
     return (cptr<T>)(p);
 }
 
-// Sum of a per-lane count over the wave (each lane's value below 2^31), as
-// a wave-uniform 64-bit value: butterfly sums within each half-wave, then
-// the two halves.
-__device__ __forceinline__ uint64_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int o = 1; o < 32; o <<= 1)
-        v += (uint32_t)__shfl_xor((int)v, o);
-    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 0) +
-           (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-}
-
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -625,10 +613,9 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
 template <int METRIC, int K>
 __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint32_t *queue, uint32_t *qcnt,
                                        uint32_t &qlen, uint32_t msk, uint32_t ent0, uint32_t lane,
-                                       uint32_t &sv_lane, uint64_t *out, uint32_t &ocount)
+                                       uint32_t &sv_item, uint64_t *out, uint32_t &ocount)
 {
     const uint32_t c = (uint32_t)__builtin_popcount(msk);
-    sv_lane += c;
     if (!__ballot(c != 0))
         return;
     if (lane == 0)
@@ -646,6 +633,7 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
             msk &= msk - 1u;
         }
         __builtin_amdgcn_wave_barrier();
+        sv_item += tot - qlen;
         qlen = tot;
         return;
     }
@@ -672,7 +660,9 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
             m &= m - 1u;
         }
         __builtin_amdgcn_wave_barrier();
-        qlen = __builtin_amdgcn_readfirstlane(*qcnt);
+        const uint32_t nlen = __builtin_amdgcn_readfirstlane(*qcnt);
+        sv_item += nlen - qlen;
+        qlen = nlen;
     }
 }
 
@@ -837,9 +827,10 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
     constexpr uint32_t kGap = pop_gap<KIND, K>();
     const uint32_t n_items = *as_const(a.wl.n_items);
     const uint32_t n_pairs = *as_const(a.wl.n_pairs);
-    // survivors of the current item, counted per lane; summed over the wave
-    // at the end of the item (band cells: (2k + 1) min(m, L) per survivor)
-    uint32_t sv_lane = 0;
+    // survivors of the current item (wave-uniform; at most qtile x slab <=
+    // 2^32 - 1 since slab < 2^22), added to the totals at the end of the
+    // item (band cells: (2k + 1) min(m, L) per survivor)
+    uint32_t sv_item = 0;
     uint64_t survivors = 0, cells = 0;
 
     // first item: the global wave index (no atomics at start-up); `wave`
@@ -889,9 +880,9 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                         mb = (e0 + 32 + col < it.de) ? mb & qm : 0u;
                     }
                     const uint32_t ent0 = ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, sv_lane, out,
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, sv_item, out,
                                       ocount);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, sv_lane,
+                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, sv_item,
                                       out, ocount);
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
@@ -926,7 +917,7 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                         m = (e0 + col < it.de) ? m & qm : 0u;
                     }
                     append<METRIC, K>(a, it, queue, &qcount[wave], qlen, m,
-                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, sv_lane,
+                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, sv_item,
                                       out, ocount);
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
@@ -978,7 +969,7 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
 #pragma unroll
                     for (uint32_t u = 0; u < 2; ++u)
                         append<METRIC, K>(a, it, queue, &qcount[wave], qlen, u ? mb : ma,
-                                          (j0 << kWordBits) | (e0 + 64 * u + lane - it.ds), lane, sv_lane, out,
+                                          (j0 << kWordBits) | (e0 + 64 * u + lane - it.ds), lane, sv_item, out,
                                           ocount);
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
@@ -987,10 +978,9 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
         }
         if (qlen)
             drain<METRIC, K>(a, it, queue, qlen, qlen, lane, out, ocount);
-        const uint64_t item_sv = wave_sum(sv_lane);
-        survivors += item_sv;
-        cells += (uint64_t)((2 * K + 1) * min(it.m, it.L)) * item_sv;
-        sv_lane = 0;
+        survivors += sv_item;
+        cells += (uint64_t)((2 * K + 1) * min(it.m, it.L)) * sv_item;
+        sv_item = 0;
         if (!PERSISTENT)
             break;
         item = next_item(a.wl.counters, nw, n_items, stripe, tries, lane, &s_done);

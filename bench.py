@@ -169,16 +169,18 @@ def match_kernel_bytes(d, q, bits: int, matches: int) -> int:
 def serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry):
     """With several batches in flight the best slab shifts (the match kernel
     shares the GPU with the other batches' small kernels): time the autotuned
-    tiles with 2 or 3 batches in flight and the slab or twice the slab, and
-    keep the fastest.  Returns (entry, batches in flight)."""
+    tiles with 1, 2 or 3 batches in flight and the slab or twice the slab,
+    and keep the fastest (one batch in flight unless more are at least 1%
+    faster: the match kernel then runs alone and its timed duration is its
+    own).  Returns (entry, batches in flight)."""
     best = None
-    for inflight in (2, 3):
+    for inflight in (1, 2, 3):
         for slab in sorted({entry["slab"], min(2 * entry["slab"], 1 << 22)}):
             e = dict(entry, slab=slab)
             plans = [fpm.fpm_plan_create(ix, nq, qbytes, metric, k, fpm.options(**e)) for _ in range(inflight)]
             ms, _, _ = time_plans(fpm, torch, plans, qb, qo, nq, 100, 2)
             del plans
-            if best is None or ms < best[0]:
+            if best is None or ms < best[0] * (0.99 if inflight > best[2] else 1.0):
                 best = (ms, e, inflight)
     log(f"serving refinement: {best[2]} in flight, slab {best[1]['slab']}, {best[0]:.3f} ms/step")
     return best[1], best[2]

@@ -270,7 +270,7 @@ struct fpm_plan {
     bool asym = false;  // asymmetric bound: query blocks ordered by popcount too
     bool survivors_only = false;
     int mx_width = 0;         // matrix-core filter over keys of this many bits (0: vector ALUs)
-    uint8_t *qexp = nullptr;  // its query rows (kMxRowBytes each, 64 padding rows)
+    uint8_t *qexp = nullptr;  // its query rows (mx_width bytes each, 64 padding rows)
 
     StrSet q;
     // asymmetric bound: the dictionary with every length block ordered by
@@ -766,6 +766,10 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     // matrix cores only when asked for
     const int key_width = ix->bits == 16 && ix->variant != FPM_COUNT ? 16 : 32;
     p->mx_width = mx_ok && p->opt.filter_unit == FPM_UNIT_MATRIX ? key_width : 0;
+    // the matrix-core kernels hold 7 blocks per compute unit (their register
+    // budget), the vector-ALU kernels 8
+    if (p->mx_width && !(opt && opt->waves_per_cu))
+        p->opt.waves_per_cu = 28;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;
@@ -781,7 +785,7 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         return hip_fail(e, "fpm_plan_create alloc");
     }
     if (p->mx_width) {
-        const size_t qb = ((size_t)max_queries + 64) * kMxRowBytes * (p->mx_width / 16);
+        const size_t qb = ((size_t)max_queries + 64) * kMxRowBytes;
         if ((e = dalloc(&p->qexp, qb)) || (e = hipMemset(p->qexp, 0, qb))) {
             plan_free(p);
             return hip_fail(e, "fpm_plan_create alloc");
@@ -833,10 +837,8 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     const bool fps = p->kind != kAll;
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
                  fps ? p->kind : kPop32, fps, p->asym, &p->ctr->err, p->scratch, s);
-    if (p->mx_width) {
-        const uint32_t t = p->kind == kQgram32 ? 4 * p->k : 2 * p->k;  // the F_D threshold
-        launch_expand_keys((const uint32_t *)p->q.key, nq, p->mx_width, t, p->qexp, s);
-    }
+    if (p->mx_width)
+        launch_expand_keys((const uint32_t *)p->q.key, nq, p->mx_width, p->qexp, s);
     if (plain) {
         uint32_t h_qoff[257];
         HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));
@@ -1209,7 +1211,7 @@ constexpr NaLayout na_layout()
     L.ctr = take(sizeof(DevCounters));
     L.keys = take(8 * kNaMaxMatches);
     L.tmp = take(8 * kNaMaxMatches);
-    L.qexp = take((size_t)(kNaMaxQueries + 64) * kMxRowBytes * 2);
+    L.qexp = take((size_t)(kNaMaxQueries + 64) * kMxRowBytes);
     L.total = o;
     return L;
 }
@@ -1304,6 +1306,8 @@ fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const
     p.kind = p.opt.schedule == FPM_SCHED_BRUTE ? kAll : ix->kind;
     const int key_width = ix->bits == 16 && ix->variant != FPM_COUNT ? 16 : 32;
     p.mx_width = p.kind != kAll && mx_ok && o.filter_unit == FPM_UNIT_MATRIX ? key_width : 0;
+    if (p.mx_width && !(opt && opt->waves_per_cu))
+        p.opt.waves_per_cu = 28;
     uint8_t *b = nd.base;
     StrSet &Q = p.q;
     Q.cap_n = kNaMaxQueries;

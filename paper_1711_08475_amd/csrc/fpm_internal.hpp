@@ -196,12 +196,11 @@ uint32_t host_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, u
 hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s);
 
-// Query side of the matrix-core filter: each of the n keys becomes a
-// kMxRowBytes-byte row of signed bytes (+1 for a clear bit, -1 for a set
-// bit) per 16 key bits (width 16: one row, 32: two), the first with the
-// threshold byte 2t + 1 - width (t: the family's F_D threshold, at most 15).
+// Query side of the matrix-core filter: each of the n keys becomes a row of
+// width (16 or 32) signed bytes, byte j = +1 for a clear bit j, -1 for a set
+// one.  The buffer holds kMxRowBytes bytes per query plus 64 padding rows.
 constexpr int kMxRowBytes = 32;
-void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s);
+void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint8_t *out, hipStream_t s);
 
 // Exact distances of explicit (query, word) pairs given as caller indices;
 // qinv / dinv map caller index -> sorted position.

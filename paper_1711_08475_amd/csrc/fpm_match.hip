@@ -667,19 +667,21 @@ __device__ __forceinline__ void append(const MatchArgs &a, const Item &it, uint3
 }
 
 // ------------------------------------------------------- matrix filter
-// F_D = popc(q ^ w) of 16-bit keys as an 8-bit integer contraction on the
-// matrix cores (v_mfma_i32_32x32x32_i8: D = A B + C, A 32 x 32 query rows,
-// B 32 x 32 word columns).  Key bit j is a signed byte: 1 - 2 q_j on the
-// query side and 2 w_j - 1 on the word side, so the 16 key positions of a
-// row-column product sum to 2 F_D - 16.  The contraction has 32 positions:
-// a lane half h (lanes 32h .. 32h + 31) holds positions 16h .. 16h + 15 of
-// its row / column, and the key occupies the first 8 of them (bits 8h ..
-// 8h + 7).  Position 8 carries the threshold: the query row holds
-// 2t - 15 there (t = 2k, 4k for bigrams) and every word column -1 (word
-// columns are -1 at all eight spare positions, the bytes of the key's
-// clear upper bits); the query row is zero at the other spare positions.
-// Each output is then 2 F_D - 2t - 1, negative iff F_D <= t, with the
-// accumulator input C = 0 (an inline constant: no register tile).
+// F_D = popc(q ^ w) of W-bit keys (W = 16 or 32) as an 8-bit integer
+// contraction on the matrix cores.  Key bit j is a signed byte: 1 - 2 q_j on
+// the query side and 2 w_j - 1 on the word side, so a row-column product
+// over the W key positions is (differing bits) - (equal bits) = 2 F_D - W.
+// One instruction covers a 32 x 32 tile with exactly W contraction
+// positions (W = 32: v_mfma_i32_32x32x32_i8, 16 bytes per lane; W = 16:
+// v_mfma_i32_32x32x16_i8, 8 bytes per lane): lane l holds row / column
+// l % 32 and the contraction bytes of half l / 32, i.e. key bits
+// (W / 2)(l / 32) .. + W / 2 - 1.  The accumulator input is the inline
+// constant W - 1 - 2t (t = 2k, bigrams 4k), so each output is
+// 2 F_D - 2t - 1, negative iff F_D <= t (Eq. 1), with no register tile and
+// no threshold position.  A pass runs two tiles; the second one takes its
+// query bytes doubled (+-2) and the constant 2W - 1 - 4t, i.e. 4 F_D - 4t -
+// 1, the same sign: two different inline constants, since one constant
+// shared by both instructions is moved into a 16-register tile.
 //
 // Output layout: lane l holds column l % 32 and, in its 16 result
 // registers r, rows 8 (r / 4) + 4 (l / 32) + r % 4.  Query rows are loaded
@@ -696,36 +698,40 @@ typedef int v16i_t __attribute__((ext_vector_type(16)));
 // first operand, selector 0 byte 0 of its second).
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t if_set, uint32_t if_clear)
 {
-    const uint32_t sel = __umul24(nib, 0x00810204u) & 0x04040404u;  // bit i -> byte i = 4 * bit
+    const uint32_t sel = __umul24(nib, 0x00810204u) & 0x04040404u;  // bit i -> byte i = 4 * bit i
     return __builtin_amdgcn_perm(if_set, if_clear, sel);
 }
 
-// The lane's word column fragment: key bits 8h .. 8h + 7 as bytes 0 .. 7
-// (word_bytes: two dwords), then -1s (position 8 meets the threshold byte
-// of the query rows).
-struct WordBytes {
-    uint32_t lo, hi;
+// Operand types of the two tile shapes.
+template <int W>
+struct MxOp;
+template <>
+struct MxOp<16> {
+    using T = long;  // 8 contraction bytes per lane
 };
-__device__ __forceinline__ WordBytes word_bytes(uint32_t w, uint32_t h)
+template <>
+struct MxOp<32> {
+    using T = v4i_t;  // 16 contraction bytes per lane
+};
+
+// The lane's word column: key bits (W / 2) h .. + W / 2 - 1 as bytes, +1
+// for a set bit and -1 for a clear one.
+template <int W>
+__device__ __forceinline__ typename MxOp<W>::T word_column(uint32_t w, uint32_t h)
 {
-    const uint32_t x = w >> (8u * h);
-    return WordBytes{nibble_bytes(x & 15u, 0x01010101u, 0xFFFFFFFFu),
-                     nibble_bytes((x >> 4) & 15u, 0x01010101u, 0xFFFFFFFFu)};
-}
-__device__ __forceinline__ v4i_t word_fragment(WordBytes b)
-{
-    // assembled per pass: a fragment kept live across the queue drains
-    // would hold four registers there instead of two; the -1s are made in
-    // the loop too (hoisted, they sit in scalar registers that the drains
-    // then spill)
-    uint32_t m1 = ~0u;
-    asm volatile("" : "+v"(b.lo), "+v"(b.hi), "+v"(m1));
-    v4i_t f;
-    f[0] = (int)b.lo;
-    f[1] = (int)b.hi;
-    f[2] = (int)m1;
-    f[3] = (int)m1;
-    return f;
+    const uint32_t x = w >> ((W / 2) * h);
+    if constexpr (W == 16) {
+        const uint32_t lo = nibble_bytes(x & 15u, 0x01010101u, 0xFFFFFFFFu);
+        const uint32_t hi = nibble_bytes((x >> 4) & 15u, 0x01010101u, 0xFFFFFFFFu);
+        return (long)(((uint64_t)hi << 32) | lo);
+    } else {
+        v4i_t f;
+        f[0] = (int)nibble_bytes(x & 15u, 0x01010101u, 0xFFFFFFFFu);
+        f[1] = (int)nibble_bytes((x >> 4) & 15u, 0x01010101u, 0xFFFFFFFFu);
+        f[2] = (int)nibble_bytes((x >> 8) & 15u, 0x01010101u, 0xFFFFFFFFu);
+        f[3] = (int)nibble_bytes((x >> 12) & 15u, 0x01010101u, 0xFFFFFFFFu);
+        return f;
+    }
 }
 
 // Shift the 16 sign bits of a tile's results into m, register 15 first.
@@ -736,20 +742,29 @@ __device__ __forceinline__ void sign_bits(const v16i_t &d, uint32_t &m)
         m = __builtin_amdgcn_alignbit(m, (uint32_t)d[r], 31);
 }
 
-// One 32 x 32 tile of 16-bit keys.
-__device__ __forceinline__ void mx_tile(v4i_t qa, v4i_t wb, uint32_t &m)
+// Query bytes +-1 -> +-2 (0x01 -> 0x02, 0xFF -> 0xFE), byte by byte.
+__device__ __forceinline__ uint32_t twice_bytes(uint32_t x) { return (x << 1) & 0xFEFEFEFEu; }
+__device__ __forceinline__ long twice_bytes(long x)
 {
-    sign_bits(__builtin_amdgcn_mfma_i32_32x32x32_i8(qa, wb, (v16i_t)(0), 0, 0, 0), m);
+    return (long)((((uint64_t)x) << 1) & 0xFEFEFEFEFEFEFEFEull);
+}
+__device__ __forceinline__ v4i_t twice_bytes(v4i_t x)
+{
+    v4i_t r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        r[i] = (int)twice_bytes((uint32_t)x[i]);
+    return r;
 }
 
-// One 32 x 32 tile of 32-bit keys: bits 0 .. 15 with the threshold position
-// (2t - 31 on the query side), then bits 16 .. 31 in the same layout with
-// no threshold, accumulated onto the first product: (2 F_D0 - 16 + 31 - 2t)
-// + (2 F_D1 - 16) = 2 F_D - 2t - 1.
-__device__ __forceinline__ void mx_tile2(v4i_t qa0, v4i_t qa1, v4i_t wb0, v4i_t wb1, uint32_t &m)
+// One 32 x 32 tile: query rows qa against word columns wb, accumulator C.
+template <int W, int C>
+__device__ __forceinline__ void mx_tile(typename MxOp<W>::T qa, typename MxOp<W>::T wb, uint32_t &m)
 {
-    const v16i_t d = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa0, wb0, (v16i_t)(0), 0, 0, 0);
-    sign_bits(__builtin_amdgcn_mfma_i32_32x32x32_i8(qa1, wb1, d, 0, 0, 0), m);
+    if constexpr (W == 16)
+        sign_bits(__builtin_amdgcn_mfma_i32_32x32x16_i8(qa, wb, (v16i_t)(C), 0, 0, 0), m);
+    else
+        sign_bits(__builtin_amdgcn_mfma_i32_32x32x32_i8(qa, wb, (v16i_t)(C), 0, 0, 0), m);
 }
 
 // ------------------------------------------------------------ schedule
@@ -804,8 +819,11 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, u
     return n_items;
 }
 
+// Eight blocks of four waves per compute unit for the vector-ALU filter
+// (64 VGPRs), seven for the matrix-core filter, whose resident query tiles
+// need up to 72.
 template <int KIND, int METRIC, int K, bool PERSISTENT, int MX>
-__global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
+__global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs a)
 {
     using F = Filter<KIND>;
     using Key = typename F::Key;
@@ -849,76 +867,35 @@ __global__ void __launch_bounds__(256, 8) k_match(MatchArgs a)
                 it.de = it.ds;
         }
         uint32_t qlen = 0;
-        if constexpr (MX == 16) {
-            // matrix cores: 64 queries x 64 words per pass, the lane's words
-            // e0 + lane % 32 and e0 + 32 + lane % 32, queries 32 (lane / 32) + b
+        if constexpr (MX != 0) {
+            // matrix cores, query-stationary: the two tiles of a group of 64
+            // queries stay in registers while the slab's words stream
+            // through, 32 per pass (lane: word e0 + lane % 32, queries
+            // 32 (lane / 32) + b of the group)
+            using Op = typename MxOp<MX>::T;
+            constexpr int kT = KIND == kQgram32 ? 4 * K : 2 * K;  // F_D threshold
+            constexpr int kC1 = MX - 1 - 2 * kT, kC0 = 2 * MX - 1 - 4 * kT;
             const uint32_t h = lane >> 5, col = lane & 31u;
             const uint32_t qrow = 32u * ((col >> 2) & 1u) + 4u * (col >> 3) + (col & 3u);
-            const uint32_t qoff = qrow * kMxRowBytes + 16u * h;  // the lane's fragment in a 64-row block
-            uint32_t wa_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
-            uint32_t wb_next = (it.ds + 32 + col < it.de) ? dkeys[it.ds + 32 + col] : 0u;
-            for (uint32_t e0 = it.ds; e0 < it.de; e0 += 64) {
-                const WordBytes xa = word_bytes(wa_next, h), xb = word_bytes(wb_next, h);
-                wa_next = (e0 + 64 + col < it.de) ? dkeys[e0 + 64 + col] : 0u;
-                wb_next = (e0 + 96 + col < it.de) ? dkeys[e0 + 96 + col] : 0u;
-                for (uint32_t j0 = 0; j0 < it.qn; j0 += 64) {
-                    const v4i_t ba = word_fragment(xa), bb = word_fragment(xb);
-                    // rows qs + j0 + 63 at most: the expanded rows carry 64 padding rows
-                    const uint8_t *qb = a.qexp + (size_t)(it.qs + j0) * kMxRowBytes;
-                    const v4i_t q0 = *(const v4i_t *)(qb + qoff);
-                    const v4i_t q1 = *(const v4i_t *)(qb + qoff + 16u * kMxRowBytes);
-                    uint32_t ma = 0, mb = 0;
-                    mx_tile(q1, ba, ma);
-                    mx_tile(q0, ba, ma);
-                    mx_tile(q1, bb, mb);
-                    mx_tile(q0, bb, mb);
-                    const uint32_t nqc = min(64u, it.qn - j0);
-                    if (nqc < 64u || e0 + 64 > it.de) {
-                        const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
-                        const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
-                        ma = (e0 + col < it.de) ? ma & qm : 0u;
-                        mb = (e0 + 32 + col < it.de) ? mb & qm : 0u;
-                    }
-                    const uint32_t ent0 = ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, ma, ent0, lane, sv_item, out,
-                                      ocount);
-                    append<METRIC, K>(a, it, queue, &qcount[wave], qlen, mb, ent0 + 32u, lane, sv_item,
-                                      out, ocount);
-                    while (qlen >= 64)
-                        drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
-                }
-            }
-        } else if constexpr (MX == 32) {
-            // matrix cores, 32-bit keys: 64 queries x 32 words per pass (two
-            // chained products per tile), the lane's word e0 + lane % 32,
-            // queries 32 (lane / 32) + b; query rows of 2 x kMxRowBytes
-            const uint32_t h = lane >> 5, col = lane & 31u;
-            const uint32_t qrow = 32u * ((col >> 2) & 1u) + 4u * (col >> 3) + (col & 3u);
-            const uint32_t qoff = qrow * (2u * kMxRowBytes) + 16u * h;
-            uint32_t w_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
-            for (uint32_t e0 = it.ds; e0 < it.de; e0 += 32) {
-                const WordBytes x0 = word_bytes(w_next, h), x1 = word_bytes(w_next >> 16, h);
-                w_next = (e0 + 32 + col < it.de) ? dkeys[e0 + 32 + col] : 0u;
-                for (uint32_t j0 = 0; j0 < it.qn; j0 += 64) {
-                    const v4i_t b0 = word_fragment(x0), b1 = word_fragment(x1);
-                    // rows qs + j0 + 63 at most: the expanded rows carry 64 padding rows
-                    const uint8_t *qb = a.qexp + (size_t)(it.qs + j0) * (2u * kMxRowBytes) + qoff;
-                    const v4i_t q00 = *(const v4i_t *)(qb);
-                    const v4i_t q01 = *(const v4i_t *)(qb + kMxRowBytes);
-                    const v4i_t q10 = *(const v4i_t *)(qb + 16u * 2u * kMxRowBytes);
-                    const v4i_t q11 = *(const v4i_t *)(qb + 16u * 2u * kMxRowBytes + kMxRowBytes);
+            for (uint32_t j0 = 0; j0 < it.qn; j0 += 64) {
+                // rows qs + j0 + 63 at most: the expanded rows carry 64 padding rows
+                const uint8_t *qb = a.qexp + (size_t)(it.qs + j0 + qrow) * MX + (MX / 2) * h;
+                const Op q0 = twice_bytes(*(const Op *)qb);
+                const Op q1 = *(const Op *)(qb + 16u * MX);
+                const uint32_t nqc = min(64u, it.qn - j0);
+                const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
+                const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
+                uint32_t w_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
+                for (uint32_t e0 = it.ds; e0 < it.de; e0 += 32) {
+                    const Op wb = word_column<MX>(w_next, h);
+                    w_next = (e0 + 32 + col < it.de) ? dkeys[e0 + 32 + col] : 0u;
                     uint32_t m = 0;
-                    mx_tile2(q10, q11, b0, b1, m);
-                    mx_tile2(q00, q01, b0, b1, m);
-                    const uint32_t nqc = min(64u, it.qn - j0);
-                    if (nqc < 64u || e0 + 32 > it.de) {
-                        const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
-                        const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
+                    mx_tile<MX, kC1>(q1, wb, m);
+                    mx_tile<MX, kC0>(q0, wb, m);
+                    if (nqc < 64u || e0 + 32 > it.de)
                         m = (e0 + col < it.de) ? m & qm : 0u;
-                    }
                     append<METRIC, K>(a, it, queue, &qcount[wave], qlen, m,
-                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, sv_item,
-                                      out, ocount);
+                                      ((j0 + 32u * h) << kWordBits) | (e0 + col - it.ds), lane, sv_item, out, ocount);
                     while (qlen >= 64)
                         drain<METRIC, K>(a, it, queue, qlen, 64, lane, out, ocount);
                 }
@@ -1190,33 +1167,27 @@ hipError_t launch_kind(const MatchArgs &a, int metric, uint32_t k, bool persiste
     return launch_kmk<KIND, 1, 3, MX>(a, persistent, pblocks, host_items, s);
 }
 
-// Query rows of the matrix filter: key bits 0 .. 7 as bytes 0 .. 7, the
-// threshold byte 2t - 15 at 8, bits 8 .. 15 as bytes 16 .. 23, zeros
-// elsewhere (1 - 2 q_j: 0x01 for a clear bit, 0xFF for a set bit).
-// 32-bit keys: two such rows per query, the second for bits 16 .. 31
-// with a zero threshold byte; the threshold byte of the first is then
-// 2t - 31, because the second part's product adds its own -16 (in general
-// 2t + 1 - 16 * parts).
-__global__ void k_expand_keys(const uint32_t *keys, uint32_t n, uint32_t t, uint32_t parts, uint8_t *out)
+// Query rows of the matrix filter: key bit j as byte j of the row, +1 for a
+// clear bit (0x01) and -1 for a set bit (0xFF); width bytes per query.
+__global__ void k_expand_keys(const uint32_t *keys, uint32_t n, uint32_t width, uint8_t *out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const uint32_t key = keys[i];
-    for (uint32_t p = 0; p < parts; ++p) {
-        const uint32_t w = key >> (16u * p);
-        uint4 lo, hi;
-        lo.x = nibble_bytes(w & 15u, 0xFFFFFFFFu, 0x01010101u);
-        lo.y = nibble_bytes((w >> 4) & 15u, 0xFFFFFFFFu, 0x01010101u);
-        lo.z = p == 0 ? (2u * t + 1u - 16u * parts) & 0xFFu : 0u;
-        lo.w = 0u;
-        hi.x = nibble_bytes((w >> 8) & 15u, 0xFFFFFFFFu, 0x01010101u);
-        hi.y = nibble_bytes((w >> 12) & 15u, 0xFFFFFFFFu, 0x01010101u);
-        hi.z = 0u;
-        hi.w = 0u;
-        uint4 *row = (uint4 *)(out + ((size_t)i * parts + p) * kMxRowBytes);
-        row[0] = lo;
-        row[1] = hi;
+    uint4 v;
+    v.x = nibble_bytes(key & 15u, 0xFFFFFFFFu, 0x01010101u);
+    v.y = nibble_bytes((key >> 4) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    v.z = nibble_bytes((key >> 8) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    v.w = nibble_bytes((key >> 12) & 15u, 0xFFFFFFFFu, 0x01010101u);
+    uint4 *row = (uint4 *)(out + (size_t)i * width);
+    row[0] = v;
+    if (width == 32) {
+        v.x = nibble_bytes((key >> 16) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        v.y = nibble_bytes((key >> 20) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        v.z = nibble_bytes((key >> 24) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        v.w = nibble_bytes((key >> 28) & 15u, 0xFFFFFFFFu, 0x01010101u);
+        row[1] = v;
     }
 }
 
@@ -1256,11 +1227,10 @@ void launch_worklist(const uint32_t *qoff, const uint32_t *doff, int metric, uin
     hipLaunchKernelGGL(k_worklist, dim3(1), dim3(256), 0, s, qoff, doff, metric, k, qtile, slab, order, tail_pct, wl);
 }
 
-void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint32_t t, uint8_t *out, hipStream_t s)
+void launch_expand_keys(const uint32_t *keys, uint32_t n, int width, uint8_t *out, hipStream_t s)
 {
     if (n)
-        hipLaunchKernelGGL(k_expand_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, t,
-                           width == 32 ? 2u : 1u, out);
+        hipLaunchKernelGGL(k_expand_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, (uint32_t)width, out);
 }
 
 hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int metric, uint32_t k, bool persistent,

@@ -1,14 +1,16 @@
 """Host-side model of the matrix-core filter's arithmetic (CPU only).
 
-F_D of 16-bit keys is computed as an 8-bit integer contraction: key bit j
-is +1 / -1 on the query side (clear / set) and -1 / +1 on the word side, so
-a row-column product over the key positions is 2 F_D - 16; one spare
-position carries 2t - 15 on the query side against -1 on the word side, so
-the product is 2 F_D - 2t - 1, negative exactly when F_D <= t (Eq. 1,
-t = 2k; bigrams 4k).  These tests rebuild the byte rows and columns, the
-32 x 32 x 32 tile's lane layout and the query-row permutation with numpy,
-and check that the sign bits land in the mask bit of the right query --
-the index arithmetic the kernel relies on, independent of the GPU."""
+F_D of W-bit keys (W = 16 or 32) is computed as an 8-bit integer
+contraction: key bit j is +1 / -1 on the query side (clear / set) and -1 /
++1 on the word side, so a row-column product over the W key positions is
+2 F_D - W; the accumulator input W - 1 - 2t makes the output 2 F_D - 2t - 1,
+negative exactly when F_D <= t (Eq. 1, t = 2k; bigrams 4k).  The second
+tile of a pass takes doubled query bytes and the constant 2W - 1 - 4t
+(output 4 F_D - 4t - 1, same sign).  These tests rebuild the byte rows and
+columns, the 32 x 32 tile's lane layout and the query-row permutation with
+numpy, and check that the sign bits land in the mask bit of the right
+query -- the index arithmetic the kernel relies on, independent of the
+GPU."""
 import numpy as np
 import pytest
 
@@ -32,21 +34,30 @@ def signed(b):
     return np.frombuffer(bytes(b), dtype=np.int8).astype(np.int64)
 
 
-def query_row(key, t, threshold_byte=None):
-    row = bytearray(32)
-    for d, nib_shift in ((0, 0), (4, 4), (16, 8), (20, 12)):
-        row[d:d + 4] = perm_bytes(0xFFFFFFFF, 0x01010101, nibble_sel((key >> nib_shift) & 15))
-    row[8] = (2 * t - 15 if threshold_byte is None else threshold_byte) & 0xFF
+def query_row(key, width):
+    """The expanded query row: byte j = +1 (0x01) for a clear bit j, -1
+    (0xFF) for a set one (nibble by nibble, as the expansion kernel)."""
+    row = bytearray(width)
+    for n in range(width // 4):
+        row[4 * n:4 * n + 4] = perm_bytes(0xFFFFFFFF, 0x01010101, nibble_sel((key >> (4 * n)) & 15))
     return signed(row)
 
 
-def word_column(key):
-    col = bytearray(32)
+def twice(row):
+    # the kernel's (x << 1) & 0xFE per byte: +1 -> +2, -1 -> -2
+    b = (row.astype(np.int64) & 0xFF)
+    return signed(bytes(int(((v << 1) & 0xFE)) for v in b))
+
+
+def word_column(key, width):
+    """Concatenation of the two lane halves' contraction bytes: half h holds
+    key bits (W / 2) h .. + W / 2 - 1, +1 for a set bit, -1 for a clear one."""
+    col = bytearray(width)
     for h in (0, 1):
-        x = key >> (8 * h)
-        col[16 * h:16 * h + 4] = perm_bytes(0x01010101, 0xFFFFFFFF, nibble_sel(x & 15))
-        col[16 * h + 4:16 * h + 8] = perm_bytes(0x01010101, 0xFFFFFFFF, nibble_sel((x >> 4) & 15))
-        col[16 * h + 8:16 * h + 16] = b"\xff" * 8
+        x = key >> ((width // 2) * h)
+        for n in range(width // 8):
+            col[(width // 2) * h + 4 * n:(width // 2) * h + 4 * n + 4] = perm_bytes(
+                0x01010101, 0xFFFFFFFF, nibble_sel((x >> (4 * n)) & 15))
     return signed(col)
 
 
@@ -56,36 +67,65 @@ def test_nibble_spread_is_exact():
         assert [(sel >> (8 * i)) & 0xFF for i in range(4)] == [4 * ((nib >> i) & 1) for i in range(4)]
 
 
+@pytest.mark.parametrize("width", [16, 32])
 @pytest.mark.parametrize("t", [2, 4, 6, 8, 12])
-def test_product_is_twice_fd_minus_threshold(t):
-    rng = np.random.default_rng(t)
-    qs = rng.integers(0, 1 << 16, 300)
-    ws = rng.integers(0, 1 << 16, 300)
+def test_product_plus_constant_is_the_threshold_test(width, t):
+    rng = np.random.default_rng(t + width)
+    qs = rng.integers(0, 1 << width, 300, dtype=np.uint64)
+    ws = rng.integers(0, 1 << width, 300, dtype=np.uint64)
     # keys near each other too, so that both signs occur
-    ws[:150] = qs[:150] ^ (1 << rng.integers(0, 16, 150)) ^ (1 << rng.integers(0, 16, 150))
-    A = np.stack([query_row(int(q), t) for q in qs])
-    B = np.stack([word_column(int(w)) for w in ws])
-    prod = A @ B.T
+    one = np.uint64(1)
+    ws[:150] = qs[:150] ^ (one << rng.integers(0, width, 150).astype(np.uint64)) ^ \
+        (one << rng.integers(0, width, 150).astype(np.uint64))
+    A = np.stack([query_row(int(q), width) for q in qs])
+    B = np.stack([word_column(int(w), width) for w in ws])
     fd = popc(qs[:, None] ^ ws[None, :])
-    assert np.array_equal(prod, 2 * fd - 2 * t - 1)
-    assert np.array_equal(prod < 0, fd <= t)
-    assert (prod < 0).any() and (prod >= 0).any()
+    prod1 = A @ B.T + (width - 1 - 2 * t)
+    assert np.array_equal(prod1, 2 * fd - 2 * t - 1)
+    prod0 = np.stack([twice(r) for r in A]) @ B.T + (2 * width - 1 - 4 * t)
+    assert np.array_equal(prod0, 4 * fd - 4 * t - 1)
+    assert np.array_equal(prod1 < 0, fd <= t) and np.array_equal(prod0 < 0, fd <= t)
+    assert (prod1 < 0).any() and (prod1 >= 0).any()
 
 
-def test_tile_layout_and_row_permutation():
-    """v_mfma_i32_32x32x32_i8 layout (lane l: A row / B column l % 32, bytes
-    16 (l / 32) .. + 15 of the contraction; result register r of lane l:
-    row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32).  With tile t's row
-    i holding query 32 ((i / 4) % 2) + 16 t + 4 (i / 8) + i % 4, shifting
-    tile 1's registers 15..0 and then tile 0's into a mask leaves bit b of
-    lane l's mask = query 32 (l / 32) + b against word l % 32."""
+def test_unused_key_positions_count_as_equal_bits():
+    """A 24-bit thermometer key (16-bit count fingerprints) in the 32-bit
+    tile: its clear top 8 bits are equal positions (-1 each), so the product
+    is still 2 F_D - 32."""
+    rng = np.random.default_rng(5)
+    qs = rng.integers(0, 1 << 24, 100)
+    ws = rng.integers(0, 1 << 24, 100)
+    A = np.stack([query_row(int(q), 32) for q in qs])
+    B = np.stack([word_column(int(w), 32) for w in ws])
+    assert np.array_equal(A @ B.T, 2 * popc(qs[:, None] ^ ws[None, :]) - 32)
+
+
+@pytest.mark.parametrize("width", [16, 32])
+def test_inline_constants_fit(width):
+    """Both accumulator constants are inline integer constants (-16 .. 64)
+    for every threshold the library uses except 16-bit bigrams at k = 3,
+    whose second constant the compiler keeps in registers."""
+    for t in (2, 4, 6, 8, 12):
+        assert -16 <= width - 1 - 2 * t <= 64
+        c0 = 2 * width - 1 - 4 * t
+        assert (-16 <= c0 <= 64) == (not (width == 16 and t == 12))
+
+
+@pytest.mark.parametrize("width", [16, 32])
+def test_tile_layout_and_row_permutation(width):
+    """32 x 32 tile layout (lane l: A row / B column l % 32, contraction
+    bytes of half l / 32; result register r of lane l: row 8 (r / 4) +
+    4 (l / 32) + r % 4, column l % 32).  With tile t's row i holding query
+    32 ((i / 4) % 2) + 16 t + 4 (i / 8) + i % 4, shifting tile 1's registers
+    15..0 and then tile 0's into a mask leaves bit b of lane l's mask =
+    query 32 (l / 32) + b against word l % 32."""
     rng = np.random.default_rng(3)
     t = 2
-    qkeys = rng.integers(0, 1 << 16, 64)
-    wkeys = rng.integers(0, 1 << 16, 32)
+    qkeys = rng.integers(0, 1 << width, 64)
+    wkeys = rng.integers(0, 1 << width, 32)
     wkeys[::3] = qkeys[:32:3] ^ 1  # some survivors
-    rows = np.stack([query_row(int(k), t) for k in qkeys])
-    cols = np.stack([word_column(int(k)) for k in wkeys])
+    rows = np.stack([query_row(int(k), width) for k in qkeys])
+    cols = np.stack([word_column(int(k), width) for k in wkeys])
 
     def qrow(i, tile):
         return 32 * ((i >> 2) & 1) + 16 * tile + 4 * (i >> 3) + (i & 3)
@@ -93,9 +133,12 @@ def test_tile_layout_and_row_permutation():
     masks = np.zeros(64, dtype=np.uint64)
     for tile in (1, 0):
         A = np.stack([rows[qrow(i, tile)] for i in range(32)])  # A[i] = row i of the tile
-        D = A @ cols.T  # D[i, j]
+        if tile == 0:
+            A = np.stack([twice(r) for r in A])
+            D = A @ cols.T + (2 * width - 1 - 4 * t)
+        else:
+            D = A @ cols.T + (width - 1 - 2 * t)
         for lane in range(64):
-            # each lane feeds its 16 contraction bytes; the product is the same
             for r in range(15, -1, -1):
                 i = 8 * (r // 4) + 4 * (lane // 32) + r % 4
                 sign = 1 if D[i, lane % 32] < 0 else 0
@@ -106,23 +149,3 @@ def test_tile_layout_and_row_permutation():
             q = 32 * h + b
             want = bin(int(qkeys[q]) ^ int(wkeys[j])).count("1") <= t
             assert ((int(masks[lane]) >> b) & 1) == int(want)
-
-
-@pytest.mark.parametrize("t", [2, 4, 6, 12])
-def test_two_part_product_for_32_bit_keys(t):
-    """32-bit keys: bits 0..15 with the threshold byte 2t - 31, then bits
-    16..31 with a zero threshold byte, the second product accumulated onto
-    the first: (2 F_D0 - 16 + 31 - 2t) + (2 F_D1 - 16) = 2 F_D - 2t - 1."""
-    rng = np.random.default_rng(40 + t)
-    qs = rng.integers(0, 1 << 32, 200, dtype=np.uint64)
-    ws = rng.integers(0, 1 << 32, 200, dtype=np.uint64)
-    ws[:100] = qs[:100] ^ (np.uint64(1) << rng.integers(0, 32, 100).astype(np.uint64))
-    A0 = np.stack([query_row(int(q) & 0xFFFF, t, 2 * t - 31) for q in qs])
-    A1 = np.stack([query_row(int(q) >> 16, t, 0) for q in qs])
-    B0 = np.stack([word_column(int(w) & 0xFFFF) for w in ws])
-    B1 = np.stack([word_column(int(w) >> 16) for w in ws])
-    prod = A0 @ B0.T + A1 @ B1.T
-    fd = popc(qs[:, None] ^ ws[None, :])
-    assert np.array_equal(prod, 2 * fd - 2 * t - 1)
-    assert np.array_equal(prod < 0, fd <= t)
-    assert (prod < 0).any() and (prod >= 0).any()

@@ -19,9 +19,12 @@ Forms timed on the same GPU (all return the same match list):
   learned      the batched form with the symbol grouping learned by the MLP
                (paper_1711_08475_amd/maps/<workload>_occ<bits>_k1.json, written
                by `python -m paper_1711_08475_amd.learn`; --train retrains it);
+  learned_matrix  the learned form with the filter test on the matrix cores
+               (an opt-in addition of this library; same survivors and matches);
   asym         (on request) the learned form under the asymmetric bound, a
                filter rule beyond the paper.
-The headline is the last form named (default: learned, the paper's rule).
+The headline is the last form named (default: learned, the paper's rule on
+the vector ALUs).
 
 Device-scheduled forms keep several batches in flight (the number is stored
 with the tiles in the tuning table; --inflight overrides): that many plans,
@@ -396,7 +399,7 @@ def run_block(fpm, torch, args, workload, variant, bits, modes, unit="auto", ext
     qbytes = int(q[1][-1])
     indexes = {"paper": ix}
     meta = None
-    if any(m in ("learned", "asym") for m in modes):
+    if any(m.replace("_matrix", "") in ("learned", "asym") for m in modes):
         indexes["learned"], meta = learned_index(fpm, d, args, workload, variant, bits, args.k)
     results, hits = {}, {}
     for mode in modes:
@@ -437,7 +440,7 @@ def main():
     ap.add_argument("-k", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="plain,brute,batched,learned",
+    ap.add_argument("--modes", default="plain,brute,batched,learned_matrix,learned",
                     help="forms to time, from plain, batched, brute, asym, learned (and learned_matrix: the "
                          "learned form with the filter on the matrix cores); the last one named is the headline")
     ap.add_argument("--no-secondary", action="store_true",

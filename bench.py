@@ -326,6 +326,16 @@ def time_form(fpm, torch, mode, ix, qb, qo, nq, qbytes, args, opts, inflight):
         raise SystemExit(f"{mode}: split and whole graphs returned different match lists")
     hits = h
     del plans
+    if graph and inflight > 1:
+        # the same kernel with one batch in flight: its duration without
+        # the other batches' kernels beside it
+        plan = fpm.fpm_plan_create(ix, nq, qbytes, args.metric, args.k, fpm.options(**dict(entry, time_kernel=1)))
+        ms_a, _, _ = time_plans(fpm, torch, [plan], qb, qo, nq, args.steps, args.warmup)
+        ka = fpm.fpm_plan_kernel_ms(plan, args.steps)
+        if not np.array_equal(fpm.fpm_plan_copy_matches(plan), hits):
+            raise SystemExit(f"{mode}: one batch in flight returned a different match list")
+        del plan
+        res["alone"] = {"ms_per_step": ms_a, "kernel_ms": float(np.mean(ka)) if ka.size else None}
     if graph:
         res["ms_per_step_kernel_timed"] = ms_t
     else:
@@ -419,7 +429,7 @@ def run_block(fpm, torch, args, workload, variant, bits, modes, unit="auto", ext
 
 
 def forms_summary(results):
-    return {m: {"pairs_per_s": v["pairs_per_s"], "ms_per_step": v["ms_per_step"],
+    return {m: {"pairs_per_s": v["pairs_per_s"], "ms_per_step": v["ms_per_step"], "one_in_flight": v.get("alone"),
                 "ms_per_step_kernel_timed": v.get("ms_per_step_kernel_timed"), "in_flight": v["inflight"],
                 "kernel_ms": v["kernel_ms"], "kernel_ms_median": v["kernel_ms_median"],
                 "examined": v["stats"]["pairs_examined"], "survivors": v["stats"]["survivors"],
@@ -497,6 +507,15 @@ def main():
         log(f"peak probes failed: {e}")
     roofline = roofline_of(st, r["kernel_ms"], args.variant, args.bits, counters, peaks,
                            match_kernel_bytes(d, q, args.bits, int(st["matches"])))
+    # with several batches in flight one launch shares the GPU with its
+    # neighbours' kernels, so its duration is not its own: the same work
+    # priced by the step time, and by the kernel's duration with one batch
+    # in flight
+    roofline["frac_step"] = roofline["ops_per_launch"] / (r["ms_per_step"] * 1e-3) / PEAK_INT_OPS
+    if r.get("alone") and r["alone"]["kernel_ms"]:
+        roofline["one_in_flight"] = {
+            "kernel_ms": r["alone"]["kernel_ms"], "ms_per_step": r["alone"]["ms_per_step"],
+            "frac": roofline["ops_per_launch"] / (r["alone"]["kernel_ms"] * 1e-3) / PEAK_INT_OPS}
 
     cpu = None
     sampled_parity = None
@@ -567,7 +586,9 @@ def main():
                        "step" if head in ("batched", "learned", "asym") else
                        "value / ms_per_step: mean over the timed steps") +
                       "; roofline kernel_ms: mean HIP-event duration of the match kernel over the same number of "
-                      "steps with the graph split around it",
+                      "steps, same batches in flight, with the graph split around it (roofline.frac_step prices the "
+                      "kernel's work by the step time, roofline.one_in_flight by its duration with one batch in "
+                      "flight)",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -313,7 +313,7 @@ void fpm_plan_destroy(fpm_plan *plan);
  * of matches.
  *
  * Every intermediate buffer lives in one static device array of the library
- * (about 28 MiB, held on each device from the first call there until the
+ * (about 26 MiB, held on each device from the first call there until the
  * process ends); the call allocates no device memory.  Limits:
  * n_queries <= FPM_NOALLOC_MAX_QUERIES, query_bytes <=
  * FPM_NOALLOC_MAX_QUERY_BYTES (FPM_EINVAL beyond them, before any device

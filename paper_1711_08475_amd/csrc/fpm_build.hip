@@ -278,7 +278,11 @@ __global__ void __launch_bounds__(256) k_fingerprints(const uint32_t *str, const
 }
 
 // k_layout followed by the fingerprint of each string, built from the
-// dwords as they are written (one pass over the bytes).
+// dwords as they are written (one pass over the bytes).  The string is read
+// as the aligned source dwords that hold its bytes -- four loads in flight
+// per step -- and each slot dword is funnel-shifted out of two neighbours
+// (v_alignbyte); every dword read holds at least one byte of the string
+// below the read limit, so no read leaves the pages of the input.
 template <int VARIANT>
 __global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const uint64_t *offsets, uint64_t nbytes_limit,
                                                    const uint32_t *perm, const uint32_t *len, const uint32_t *off,
@@ -308,17 +312,39 @@ __global__ void __launch_bounds__(256) k_layout_fp(const uint8_t *bytes, const u
         const uint64_t start = offsets[i];
         const uint64_t end_all = offsets[n];
         const uint64_t limit = end_all < nbytes_limit ? end_all : nbytes_limit;
-        for (uint32_t t = 0; t < sw; ++t) {
-            uint32_t w = 0;
+        // bytes of the string below the read limit; the rest of the slot is zero
+        const uint32_t le = start >= limit ? 0u : (uint32_t)min((uint64_t)L, limit - start);
+        const uintptr_t a0 = (uintptr_t)(bytes + start);
+        const uint32_t *src = (const uint32_t *)(a0 & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a0 & 3u);
+        const uint32_t nsrc = (sh + le + 3u) >> 2;  // source dwords holding bytes of the string
+        uint32_t cur = nsrc ? src[0] : 0u;
+        for (uint32_t t = 0; t < sw; t += 4) {
+            uint32_t nx[4], w[4];
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t pos = 4 * t + j;
-                const uint64_t a = start + pos;
-                if (pos < L && a < limit)
-                    w |= (uint32_t)bytes[a] << (8 * j);
+            for (uint32_t u = 0; u < 4; ++u)
+                nx[u] = (t + u + 1 < nsrc) ? src[t + u + 1] : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t lo = u ? nx[u - 1] : cur;
+                const int rem = (int)le - 4 * (int)(t + u);
+                const uint32_t m = rem >= 4 ? ~0u : (rem <= 0 ? 0u : (1u << (8u * (uint32_t)rem)) - 1u);
+                w[u] = __builtin_amdgcn_alignbyte(nx[u], lo, sh) & m;
             }
-            str[so + t] = w;
-            fp_dword<VARIANT>(fp, prev, w, t, L, smap, npos);
+            cur = nx[3];
+            if (sw >= 4) {  // whole 16-byte groups (slots of 4 ceil(L / 16) dwords, 16-byte aligned)
+                *(uint4 *)(str + so + t) = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    fp_dword<VARIANT>(fp, prev, w[u], t + u, L, smap, npos);
+            } else {  // L <= 8: one or two dwords
+                str[so] = w[0];
+                fp_dword<VARIANT>(fp, prev, w[0], 0, L, smap, npos);
+                if (sw > 1) {
+                    str[so + 1] = w[1];
+                    fp_dword<VARIANT>(fp, prev, w[1], 1, L, smap, npos);
+                }
+            }
         }
     }
     if (fp_orig)

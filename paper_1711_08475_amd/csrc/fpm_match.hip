@@ -587,9 +587,9 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     const uint32_t tq = ent >> kWordBits, te = ent & ((1u << kWordBits) - 1u);
     uint32_t d = K + 1;
     if (act) {
-        d = a.survivors_only ? 0u
-                             : verify<METRIC, K>(a.q.str + it.qslot + __umul24(tq, it.qsw), it.m,
-                                                 a.d.str + it.dslot + __umul24(te, it.dsw), it.L);
+        // 32-bit slot offsets (unsigned: no sign extension into the address)
+        const uint32_t qo = it.qslot + (uint32_t)__umul24(tq, it.qsw), wo = it.dslot + (uint32_t)__umul24(te, it.dsw);
+        d = a.survivors_only ? 0u : verify<METRIC, K>(a.q.str + qo, it.m, a.d.str + wo, it.L);
     }
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);

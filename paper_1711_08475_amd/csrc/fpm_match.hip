@@ -163,6 +163,12 @@ __device__ __forceinline__ uint32_t opaque_s(uint32_t x)
     asm("" : "+s"(x));
     return x;
 }
+template <typename T>
+__device__ __forceinline__ T *opaque_ptr(T *p)
+{
+    asm("" : "+s"(p));
+    return p;
+}
 
 template <>
 struct Filter<kAsym32> {
@@ -506,6 +512,18 @@ __device__ __forceinline__ cptr<T> as_const(const T *p)
     return (cptr<T>)(p);
 }
 
+// The match kernel's arguments, read from the kernel-argument segment where
+// they are used (the match-list flushes and the block epilogue, a few times
+// per wave): the empty asm makes each use a fresh scalar load, so that these
+// values hold no scalar registers across the loops.  The vector-filter
+// kernel has 80 scalar registers at eight waves per SIMD.
+__device__ __forceinline__ cptr<MatchArgs> kargs()
+{
+    uint64_t p = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return (cptr<MatchArgs>)p;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -517,8 +535,9 @@ struct Item {
     uint32_t qs, qn;        // sorted query range
     uint32_t ds, de;        // sorted dictionary range
     uint32_t m, L;          // query length, word length
-    uint32_t qslot, dslot;  // dword offsets of the first query / word slot
     uint32_t qsw, dsw;      // slot sizes in dwords
+    const uint32_t *qstr, *dstr;    // slots of the item's first query / word
+    const uint32_t *qperm, *dperm;  // caller indices from the item's first query / word on
 };
 
 __device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, uint32_t n_pairs)
@@ -545,8 +564,10 @@ __device__ __forceinline__ Item decode_item(const MatchArgs &a, uint32_t item, u
     it.de = min(it.ds + slab, dbase + nd);
     it.m = pairs[lo].qlen;
     it.L = pairs[lo].dlen;
-    it.qslot = as_const(a.q.soff)[it.qs];
-    it.dslot = as_const(a.d.soff)[it.ds];
+    it.qstr = a.q.str + as_const(a.q.soff)[it.qs];
+    it.dstr = a.d.str + as_const(a.d.soff)[it.ds];
+    it.qperm = a.q.perm + it.qs;
+    it.dperm = a.d.perm + it.ds;
     it.qsw = slot_dwords(it.m);
     it.dsw = slot_dwords(it.L);
     return it;
@@ -560,14 +581,15 @@ constexpr uint32_t kWordBits = 22;
 __device__ __forceinline__ void flush(const MatchArgs &a, const uint64_t *out, uint32_t &ocount, uint32_t lane)
 {
     __builtin_amdgcn_wave_barrier();
+    const cptr<MatchArgs> A = kargs();
     unsigned long long base = 0;
     if (lane == 0)
-        base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)ocount);
+        base = atomicAdd((unsigned long long *)A->ctr.n_out, (unsigned long long)ocount);
     base = __shfl(base, 0);
     for (uint32_t i = lane; i < ocount; i += 64) {
         const uint64_t idx = base + i;
-        if (idx < a.out_cap)
-            a.out_keys[idx] = out[i];
+        if (idx < A->out_cap)
+            A->out_keys[idx] = out[i];
     }
     __builtin_amdgcn_wave_barrier();
     ocount = 0;
@@ -588,15 +610,15 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     uint32_t d = K + 1;
     if (act) {
         // 32-bit slot offsets (unsigned: no sign extension into the address)
-        const uint32_t qo = it.qslot + (uint32_t)__umul24(tq, it.qsw), wo = it.dslot + (uint32_t)__umul24(te, it.dsw);
-        d = a.survivors_only ? 0u : verify<METRIC, K>(a.q.str + qo, it.m, a.d.str + wo, it.L);
+        const uint32_t qo = (uint32_t)__umul24(tq, it.qsw), wo = (uint32_t)__umul24(te, it.dsw);
+        d = a.survivors_only ? 0u : verify<METRIC, K>(it.qstr + qo, it.m, it.dstr + wo, it.L);
     }
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);
     if (mm) {
         if (ok)
-            out[ocount + lanes_below(mm)] = ((uint64_t)a.q.perm[it.qs + tq] << (a.wbits + 2)) |
-                                            ((uint64_t)a.d.perm[it.ds + te] << 2) | d;
+            out[ocount + lanes_below(mm)] = ((uint64_t)it.qperm[tq] << (a.wbits + 2)) |
+                                            ((uint64_t)it.dperm[te] << 2) | d;
         ocount += (uint32_t)__popcll(mm);
         if (ocount > (uint32_t)kOutFlush)
             flush(a, out, ocount, lane);
@@ -823,8 +845,25 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t nw, u
 // (64 VGPRs), seven for the matrix-core filter, whose resident query tiles
 // need up to 72.
 template <int KIND, int METRIC, int K, bool PERSISTENT, int MX>
-__global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs a)
+__global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
 {
+    // The pointers used inside the loops, taken as plain values: the compiler
+    // would otherwise repeat their loads from the kernel-argument segment
+    // inside the loops instead of keeping them (a long-latency scalar load,
+    // which the next wait on an LDS result also waits for).  Per-item
+    // pointers (Item) replace base pointer + offset pairs in the drain, so
+    // the filter loop keeps its own values in scalar registers.
+    MatchArgs a = args;
+    a.q.key = opaque_ptr(a.q.key);
+    a.d.key = opaque_ptr(a.d.key);
+    a.q.str = opaque_ptr(a.q.str);
+    a.d.str = opaque_ptr(a.d.str);
+    a.q.perm = opaque_ptr(a.q.perm);
+    a.d.perm = opaque_ptr(a.d.perm);
+    a.q.soff = opaque_ptr(a.q.soff);
+    a.d.soff = opaque_ptr(a.d.soff);
+    a.wl.pairs = opaque_ptr(a.wl.pairs);
+    a.wl.counters = opaque_ptr(a.wl.counters);
     using F = Filter<KIND>;
     using Key = typename F::Key;
     __shared__ __attribute__((aligned(16))) uint32_t queue_all[kWaves][kQueueCap];
@@ -986,20 +1025,21 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs a)
             red[3 * w + 2] = o;  // exclusive prefix: the wave's first output slot
             o += cnt[w];
         }
+        const cptr<MatchArgs> A = kargs();
         unsigned long long base = 0;
         if (o)
-            base = atomicAdd((unsigned long long *)a.ctr.n_out, (unsigned long long)o);
+            base = atomicAdd((unsigned long long *)A->ctr.n_out, (unsigned long long)o);
         if (sv)
-            atomicAdd((unsigned long long *)a.ctr.survivors, (unsigned long long)sv);
+            atomicAdd((unsigned long long *)A->ctr.survivors, (unsigned long long)sv);
         if (ce)
-            atomicAdd((unsigned long long *)a.ctr.verify_cells, (unsigned long long)ce);
+            atomicAdd((unsigned long long *)A->ctr.verify_cells, (unsigned long long)ce);
         red[3 * kWaves] = base;
     }
     __syncthreads();
     const uint64_t base = red[3 * kWaves] + red[3 * wave + 2];
     for (uint32_t i = lane; i < ocount; i += 64) {
-        if (base + i < a.out_cap)
-            a.out_keys[base + i] = out[i];
+        if (base + i < kargs()->out_cap)
+            kargs()->out_keys[base + i] = out[i];
     }
 }
 

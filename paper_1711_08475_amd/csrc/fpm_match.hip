@@ -284,10 +284,13 @@ __device__ __forceinline__ bool pop_apart(uint32_t alo, uint32_t ahi, uint32_t b
 // 16 bytes at a time.
 
 // Dwords g0 .. g0+D-1 of a string (load_raw), then bytes at positions >=
-// len cleared (mask_tail).  The verifiers issue every load of a step before
-// any mask (one memory round trip); loads may run up to four dwords past
-// the string's slot, which the string buffers' tail slack covers.  len is
-// wave-uniform in the match kernel, so the masks are scalar.
+// len cleared (mask_tail).  Every layout kernel writes whole slots, zero
+// beyond the string's length, so only a dword past the slot needs the mask:
+// the Lev k = 1 test's one extra dword of the longer string, which may lie in
+// the next slot (the string buffers' tail slack covers a read past the last
+// one).  The verifiers issue every load of a step before any mask (one
+// memory round trip); len is wave-uniform in the match kernel, so the masks
+// are scalar.
 template <int D>
 __device__ __forceinline__ void load_raw(const uint32_t *p, uint32_t g0, uint32_t (&v)[D])
 {
@@ -316,14 +319,13 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t x)
     return (uint32_t)__builtin_popcount((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
 }
 
+// Dwords g0 .. g0+D-1 of two strings of one length lie inside both slots.
 template <int D>
-__device__ __forceinline__ uint32_t ham_dwords(const uint32_t *a, const uint32_t *b, uint32_t g0, uint32_t m)
+__device__ __forceinline__ uint32_t ham_dwords(const uint32_t *a, const uint32_t *b, uint32_t g0)
 {
     uint32_t A[D], B[D];
     load_raw<D>(a, g0, A);
     load_raw<D>(b, g0, B);
-    mask_tail<D>(g0, m, A);
-    mask_tail<D>(g0, m, B);
     uint32_t d = 0;
 #pragma unroll
     for (int t = 0; t < D; ++t)
@@ -337,14 +339,14 @@ __device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, const uint32_t
 {
     uint32_t d;
     if (m <= 4) {
-        d = ham_dwords<1>(a, b, 0, m);
+        d = ham_dwords<1>(a, b, 0);
     } else if (m <= 8) {
-        d = ham_dwords<2>(a, b, 0, m);
+        d = ham_dwords<2>(a, b, 0);
     } else {
         d = 0;
         const uint32_t nch = (m + 15) >> 4;
         for (uint32_t c = 0; c < nch; ++c) {
-            d += ham_dwords<4>(a, b, 4 * c, m);
+            d += ham_dwords<4>(a, b, 4 * c);
             if (!__any(d <= (uint32_t)K))
                 break;
         }
@@ -354,7 +356,9 @@ __device__ __forceinline__ uint32_t verify_ham(const uint32_t *a, const uint32_t
 
 // One group of D dwords of the Lev k = 1 test for lengths m and n = m + 1
 // (a shorter): first_a tracks the first j with a[j] != b[j] (clamped to m),
-// last_b the last j with a[j] != b[j + 1].
+// last_b the last j with a[j] != b[j + 1].  Dwords g0 .. g0+D-1 lie inside
+// both slots (slot_dwords(m + 1) >= slot_dwords(m)); b's dword g0 + D may
+// not, and is masked.
 template <int D>
 __device__ __forceinline__ void lev1_dwords(const uint32_t *a, const uint32_t *b, uint32_t g0, uint32_t m,
                                             uint32_t &first_a, int &last_b)
@@ -362,8 +366,8 @@ __device__ __forceinline__ void lev1_dwords(const uint32_t *a, const uint32_t *b
     uint32_t A[D], B[D + 1];
     load_raw<D>(a, g0, A);
     load_raw<D + 1>(b, g0, B);
-    mask_tail<D>(g0, m, A);
-    mask_tail<D + 1>(g0, m + 1, B);
+    uint32_t (&Bx)[1] = *reinterpret_cast<uint32_t (*)[1]>(&B[D]);
+    mask_tail<1>(g0 + D, m + 1, Bx);
 #pragma unroll
     for (int t = 0; t < D; ++t) {
         const uint32_t xa = A[t] ^ B[t];

@@ -119,13 +119,17 @@ def roofline_of(st: dict, kernel_ms, variant: str, bits: int, counters, peaks=No
     """Roofline of the match kernel.  Algorithmic work per launch = filter
     ops per examined pair x examined pairs + band cells (2k+1) min(m, n) of
     the survivors, over the kernel's measured duration, against the
-    published int-VALU peak -- whichever unit ran the filter test.  Issued
-    VALU utilisation (from the committed counters) and, when the matrix
-    cores ran the filter, their int8 fraction are reported beside it under
-    their own names.  `peaks` (fpm_measure_peaks) adds the peaks measured on
-    this device; `hbm_bytes` the kernel's algorithmic HBM bytes."""
+    published int-VALU peak -- whichever unit ran the filter test.  When
+    popcount pruning skipped pairs (which fail the filter without a test),
+    the same pricing over the pairs the filter tested is reported beside it
+    as `frac_tested`.  Issued VALU utilisation (from the committed counters)
+    and, when the matrix cores ran the filter, their int8 fraction are
+    reported under their own names.  `peaks` (fpm_measure_peaks) adds the
+    peaks measured on this device; `hbm_bytes` the kernel's algorithmic HBM
+    bytes."""
     matrix = st.get("filter_unit") == FPM_UNIT_MATRIX
     per_pair = filter_ops(variant, bits)
+    tested = st.get("pairs_filtered") or st["pairs_examined"]
     ops = per_pair * st["pairs_examined"] + st["verify_cells"]
     achieved = ops / (kernel_ms * 1e-3) if kernel_ms else None
     roofline = {
@@ -138,9 +142,13 @@ def roofline_of(st: dict, kernel_ms, variant: str, bits: int, counters, peaks=No
         "kernel": "k_match (fused filter + LDS queue + verify)",
         "filter_unit": "matrix" if matrix else "valu",
         "filter_ops_per_pair": per_pair,
+        "pairs_examined": st["pairs_examined"],
+        "pairs_tested": tested,
         "ops_per_launch": ops,
         "kernel_ms": kernel_ms,
     }
+    if tested < st["pairs_examined"] and kernel_ms:
+        roofline["frac_tested"] = (per_pair * tested + st["verify_cells"]) / (kernel_ms * 1e-3) / PEAK_INT_OPS
     if peaks:
         roofline["peak_measured"] = peaks["int_valu_ops_per_s"] / 1e12
     if counters and counters.get("valu_insts_per_launch") and kernel_ms:
@@ -424,7 +432,7 @@ def run_block(fpm, torch, args, workload, variant, bits, modes, unit="auto", ext
         st = r["stats"]
         log(f"{mode}: {r['ms_per_step']:.3f} ms/step ({inflight} in flight), kernel {r['kernel_ms']:.3f} ms, "
             f"{r['pairs_per_s']:.3e} pairs/s, survivors {st['survivors']}, matches {h.shape[0]}, "
-            f"filter unit {st['filter_unit']}")
+            f"filter unit {st['filter_unit']}, pairs tested {st['pairs_filtered']} of {st['pairs_examined']}")
     return results, hits, {"d": d, "q": q, "fp_build": fp_build, "learned_meta": meta}
 
 
@@ -432,8 +440,8 @@ def forms_summary(results):
     return {m: {"pairs_per_s": v["pairs_per_s"], "ms_per_step": v["ms_per_step"], "one_in_flight": v.get("alone"),
                 "ms_per_step_kernel_timed": v.get("ms_per_step_kernel_timed"), "in_flight": v["inflight"],
                 "kernel_ms": v["kernel_ms"], "kernel_ms_median": v["kernel_ms_median"],
-                "examined": v["stats"]["pairs_examined"], "survivors": v["stats"]["survivors"],
-                "matches": v["stats"]["matches"],
+                "examined": v["stats"]["pairs_examined"], "tested": v["stats"]["pairs_filtered"],
+                "survivors": v["stats"]["survivors"], "matches": v["stats"]["matches"],
                 "filter_unit": {0: "none", 1: "valu", 2: "matrix"}[v["stats"]["filter_unit"]]}
             for m, v in results.items()}
 

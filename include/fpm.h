@@ -113,22 +113,41 @@ typedef enum { FPM_BOUND_FD = 0, FPM_BOUND_ASYM = 1 } fpm_bound;
  *     shift of the result's sign bit into a survivor mask.
  *   FPM_UNIT_MATRIX (opt-in, an addition of this library: the method is
  *     integer bit arithmetic and the paper's design has no matrix unit):
- *     matrix cores; FPM_EUNSUPPORTED where the key family
- *     does not allow it.  F_D of two bit vectors is an inner product: with
+ *     matrix cores; FPM_EUNSUPPORTED where the key family does not allow
+ *     it.  F_D of two W-bit keys (W = 16 or 32) is an inner product: with
  *     every key bit written as a signed byte (+1 for 0, -1 for 1 on the
  *     query side, the negation on the word side), the product of a query
- *     row and a word column over 16 key positions is 2 F_D - 16.  One
- *     8-bit integer matrix instruction (32 x 32 outputs, 32 contraction
- *     positions) takes 16 key bits and, in a spare position, the threshold
- *     term, and yields 2 F_D - 2t - 1 for 1,024 pairs, negative exactly
- *     when the pair survives (32-bit keys: two instructions per tile, the
- *     second accumulating bits 16..31 onto the first); the sign bits go
- *     into the same survivor masks as on the vector path.  Offered for the
- *     paper's rule (FPM_BOUND_FD) on keys whose F_D is the popcount of
- *     their XOR: occurrence and occurrence-halved fingerprints (16 and 32
- *     bits), 16-bit count fingerprints (24-bit thermometer keys) and
- *     bigrams.  Survivors and matches are the same on both units. */
+ *     row and a word column over the W key positions is 2 F_D - W.  One
+ *     8-bit integer matrix instruction (32 x 32 outputs, W contraction
+ *     positions) with the accumulator input W - 1 - 2t yields 2 F_D - 2t - 1
+ *     for 1,024 pairs, negative exactly when the pair survives; a group of
+ *     64 queries stays in registers while the words stream through, and the
+ *     sign bits go into the same survivor masks as on the vector path.
+ *     Offered for the paper's rule (FPM_BOUND_FD) on keys whose F_D is the
+ *     popcount of their XOR: occurrence and occurrence-halved fingerprints
+ *     (16 and 32 bits), 16-bit count fingerprints (24-bit thermometer keys)
+ *     and bigrams.  Survivors and matches are the same on both units. */
 typedef enum { FPM_UNIT_AUTO = 0, FPM_UNIT_VALU = 1, FPM_UNIT_MATRIX = 2 } fpm_filter_unit;
+
+/* Popcount pruning of the paper's rule (an exact shortcut, not in the
+ * paper).  F_D = popc(q ^ w) >= |popc(q) - popc(w)|, so a pair whose key
+ * popcounts differ by more than t (Eq. 1: 2k, bigrams 4k) fails the filter.
+ * With pruning, a plan orders every length block of its dictionary copy
+ * and of each query batch by key popcount; a group of pairs (a work item,
+ * or 32 queries x 128 words) whose popcount ranges lie more than t apart is
+ * skipped untested.  Survivors, matches and pairs_examined are unchanged;
+ * fpm_stats.pairs_filtered counts the pairs the filter actually tested.
+ * The ordering also gathers the survivors into the work items near equal
+ * popcounts, so pruning pays where the key popcounts are spread (long and
+ * mixed-length strings) and wants smaller work items than the unordered
+ * layout; the tuning table records where it is on.
+ *   FPM_PRUNE_OFF (default): every examined pair is tested.
+ *   FPM_PRUNE_ON: the batched schedule on the vector ALUs with occurrence,
+ *     occurrence-halved, count or bigram keys under FPM_BOUND_FD;
+ *     FPM_EUNSUPPORTED otherwise.  The plan then holds a popcount-ordered
+ *     copy of the dictionary's strings, keys and permutation (about the
+ *     index's own size). */
+typedef enum { FPM_PRUNE_OFF = 0, FPM_PRUNE_ON = 1 } fpm_pop_prune;
 
 /* One reported match.  `query` and `word` index the caller's lists. */
 typedef struct {
@@ -144,6 +163,8 @@ typedef struct {
     uint64_t survivors;      /* pairs kept by the filter (F_D <= 2k, or the asymmetric bound) and verified */
     uint64_t matches;        /* pairs within distance k */
     uint64_t verify_cells;   /* sum over survivors of (2k+1) * min(m, n) */
+    uint64_t pairs_filtered; /* examined pairs the filter tested (the rest were skipped by popcount
+                                pruning, which no survivor can be; 0 for FPM_SCHED_BRUTE) */
     float ms;                /* device time of the match pipeline (hip events) */
     uint32_t work_items;     /* work items the schedule processed */
     uint32_t filter_unit;    /* fpm_filter_unit that ran the filter test: FPM_UNIT_VALU or FPM_UNIT_MATRIX
@@ -169,7 +190,8 @@ typedef struct {
                                   ends on short items; 0 = default (100: no tail items) */
     uint32_t bound;            /* fpm_bound: filter rule (default FPM_BOUND_FD); ignored by FPM_SCHED_BRUTE */
     uint32_t filter_unit;      /* fpm_filter_unit: where the filter test runs (default FPM_UNIT_AUTO) */
-    uint32_t reserved[5];
+    uint32_t pop_prune;        /* fpm_pop_prune (default FPM_PRUNE_OFF) */
+    uint32_t reserved[4];
 } fpm_options;
 
 typedef struct fpm_index fpm_index;

@@ -233,7 +233,7 @@ void prep_strings(StrSet &S, const uint8_t *d_bytes, const uint64_t *d_offsets, 
 }
 
 struct DevCounters {
-    uint64_t n_out, survivors, cells, examined;
+    uint64_t n_out, survivors, cells, examined, pruned;
     uint32_t err, n_pairs, n_items, pad;
     uint32_t counters[kStripes * kStripeStride];  // persistent work counters
 };
@@ -267,15 +267,17 @@ struct fpm_plan {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int kind = kPop32;
-    bool asym = false;  // asymmetric bound: query blocks ordered by popcount too
+    bool asym = false;   // asymmetric bound: query blocks ordered by popcount too
+    bool prune = false;  // the paper's rule over popcount-ordered blocks (kernel kind pop_pruned_kind(kind))
+    bool pop = false;    // asym || prune: dictionary and query blocks ordered by key popcount
     bool survivors_only = false;
     int mx_width = 0;         // matrix-core filter over keys of this many bits (0: vector ALUs)
     uint8_t *qexp = nullptr;  // its query rows (mx_width bytes each, 64 padding rows)
 
     StrSet q;
-    // asymmetric bound: the dictionary with every length block ordered by
-    // key popcount (own strings, permutation and keys; lengths, slot offsets
-    // and block tables are the index's)
+    // asymmetric bound or popcount pruning: the dictionary with every length
+    // block ordered by key popcount (own strings, permutation and keys;
+    // lengths, slot offsets and block tables are the index's)
     uint32_t *a_perm = nullptr, *a_str = nullptr;
     void *a_key = nullptr;
     uint32_t *scratch = nullptr;
@@ -686,13 +688,16 @@ static fpm_status resolve_options(const fpm_options *in, fpm_options *o)
         return fail(FPM_EINVAL, "unknown bound %u", o->bound);
     if (o->filter_unit > FPM_UNIT_MATRIX)
         return fail(FPM_EINVAL, "unknown filter unit %u", o->filter_unit);
+    if (o->pop_prune > FPM_PRUNE_ON)
+        return fail(FPM_EINVAL, "unknown pop_prune %u", o->pop_prune);
     return FPM_OK;
 }
 
-// The dictionary of an asymmetric-bound plan: the index's length blocks,
-// each ordered by key popcount (stable), with keys of the bound's family.
-// Runs once at plan creation and waits for it.
-static fpm_status build_asym_dictionary(fpm_plan *p)
+// The dictionary of a plan over popcount-ordered blocks (asymmetric bound or
+// popcount pruning): the index's length blocks, each ordered by key popcount
+// (stable), with keys of the plan's family.  Runs once at plan creation and
+// waits for it.
+static fpm_status build_pop_dictionary(fpm_plan *p)
 {
     const fpm_index *ix = p->ix;
     const StrSet &W = ix->words;
@@ -703,7 +708,7 @@ static fpm_status build_asym_dictionary(fpm_plan *p)
     if ((e = dalloc(&p->a_perm, std::max<uint32_t>(n, 1))) || (e = dalloc(&p->a_str, W.str_cap)) ||
         (e = dalloc((uint8_t **)&p->a_key, kb)) ||
         (e = hipMemsetAsync(p->a_str, 0, W.str_cap * sizeof(uint32_t), s)) || (e = hipMemsetAsync(p->a_key, 0, kb, s)))
-        return hip_fail(e, "asymmetric-bound dictionary alloc");
+        return hip_fail(e, "popcount-ordered dictionary alloc");
     launch_pop_order(W.off, W.bdw, W.str, W.perm, W.key, ix->kind, p->a_str, p->a_perm, p->a_key, s);
     if (p->kind == kTherm32)  // the moved keys are the plain ones: extend them
         launch_fingerprints(p->a_str, W.soff, W.slen, p->a_perm, n, ix->d_map, ix->variant, (int)ix->bits, nullptr,
@@ -712,7 +717,7 @@ static fpm_status build_asym_dictionary(fpm_plan *p)
     if (!e)
         e = hipGetLastError();
     if (e)
-        return hip_fail(e, "asymmetric-bound dictionary");
+        return hip_fail(e, "popcount-ordered dictionary");
     return FPM_OK;
 }
 
@@ -770,6 +775,17 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     // budget), the vector-ALU kernels 8
     if (p->mx_width && !(opt && opt->waves_per_cu))
         p->opt.waves_per_cu = 28;
+    // popcount pruning (on request): the batched schedule on the vector
+    // ALUs, for keys whose F_D is the popcount of their XOR
+    const bool prune_ok = !p->asym && !p->mx_width && p->opt.schedule == FPM_SCHED_BATCHED &&
+                          pop_pruned_kind(p->kind) >= 0;
+    if (p->opt.pop_prune == FPM_PRUNE_ON && !prune_ok) {
+        delete p;
+        return fail(FPM_EUNSUPPORTED, "popcount pruning takes the batched schedule on the vector ALUs with "
+                                      "occurrence, occurrence-halved, count or bigram fingerprints and the paper's rule");
+    }
+    p->prune = p->opt.pop_prune == FPM_PRUNE_ON;
+    p->pop = p->asym || p->prune;
     hipError_t e = hipSuccess;
     if (hip_stream) {
         p->stream = (hipStream_t)hip_stream;
@@ -778,7 +794,7 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
         p->own_stream = true;
     }
     const int qkind = p->kind == kAll ? kPop32 : p->kind;
-    if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false, p->asym)) ||
+    if (e || (e = p->q.alloc(max_queries, max_query_bytes, qkind, false, false, p->pop)) ||
         (e = dalloc(&p->scratch, kRadixScratch)) || (e = dalloc(&p->pairs, kMaxPairs)) ||
         (e = dalloc(&p->ctr, 1)) || (e = hipEventCreate(&p->ev0)) || (e = hipEventCreate(&p->ev1))) {
         plan_free(p);
@@ -791,10 +807,10 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
             return hip_fail(e, "fpm_plan_create alloc");
         }
     }
-    p->q.pop_ordered = p->asym;
+    p->q.pop_ordered = p->pop;
     st = p->alloc_output(p->opt.match_capacity);
-    if (!st && p->asym)
-        st = build_asym_dictionary(p);
+    if (!st && p->pop)
+        st = build_pop_dictionary(p);
     if (st) {
         plan_free(p);
         return st;
@@ -836,7 +852,7 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     launch_zero(p->ctr, sizeof(DevCounters) / 4, s);
     const bool fps = p->kind != kAll;
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
-                 fps ? p->kind : kPop32, fps, p->asym, &p->ctr->err, p->scratch, s);
+                 fps ? p->kind : kPop32, fps, p->pop, &p->ctr->err, p->scratch, s);
     if (p->mx_width)
         launch_expand_keys((const uint32_t *)p->q.key, nq, p->mx_width, p->qexp, s);
     if (plain) {
@@ -865,20 +881,20 @@ static fpm_status enqueue_kernel(fpm_plan *p, bool plain)
     MatchArgs a;
     a.q = p->q.view();
     a.d = ix->words.view();
-    if (p->asym) {
+    if (p->pop) {
         a.d.perm = p->a_perm;
         a.d.str = p->a_str;
         a.d.key = p->a_key;
     }
     a.wl = p->worklist();
-    a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells};
+    a.ctr = MatchCounters{&p->ctr->n_out, &p->ctr->survivors, &p->ctr->cells, &p->ctr->pruned};
     a.out_keys = p->keys;
     a.out_cap = p->cap;
     a.wbits = ix->wbits;
     a.survivors_only = p->survivors_only ? 1u : 0u;
     a.qexp = p->qexp;
-    hipError_t e = launch_match(a, p->kind, p->mx_width, p->metric, p->k, !plain, (uint32_t)p->persistent_blocks,
-                                p->host_items, p->stream);
+    hipError_t e = launch_match(a, p->prune ? pop_pruned_kind(p->kind) : p->kind, p->mx_width, p->metric, p->k,
+                                !plain, (uint32_t)p->persistent_blocks, p->host_items, p->stream);
     if (e)
         return hip_fail(e, "match kernel launch");
     return FPM_OK;
@@ -1054,6 +1070,7 @@ fpm_status fpm_plan_result(fpm_plan *p, const fpm_hit **d_matches, uint64_t *n_o
     st.survivors = c.survivors;
     st.matches = c.n_out;
     st.verify_cells = c.cells;
+    st.pairs_filtered = p->kind == kAll ? 0 : c.examined - std::min(c.pruned, c.examined);
     st.ms = ms;
     st.work_items = c.n_items;
     st.filter_unit = p->kind == kAll ? FPM_UNIT_AUTO : p->mx_width ? FPM_UNIT_MATRIX : FPM_UNIT_VALU;
@@ -1260,6 +1277,8 @@ fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const
         return st;
     if (o.bound == FPM_BOUND_ASYM && o.schedule != FPM_SCHED_BRUTE)
         return fail(FPM_EUNSUPPORTED, "the allocation-free match takes the paper's rule only");
+    if (o.pop_prune == FPM_PRUNE_ON)
+        return fail(FPM_EUNSUPPORTED, "the allocation-free match has no popcount-ordered dictionary");
     const bool mx_ok = ix->kind == kPop32 || ix->kind == kQgram32;
     if (o.filter_unit == FPM_UNIT_MATRIX && o.schedule != FPM_SCHED_BRUTE && !mx_ok)
         return fail(FPM_EUNSUPPORTED, "the matrix-core filter takes the paper's rule on occurrence, "
@@ -1357,6 +1376,7 @@ fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const
     sres.survivors = c.survivors;
     sres.matches = c.n_out;
     sres.verify_cells = c.cells;
+    sres.pairs_filtered = p.kind == kAll ? 0 : c.examined - std::min(c.pruned, c.examined);
     sres.work_items = c.n_items;
     sres.filter_unit = p.kind == kAll ? FPM_UNIT_AUTO : p.mx_width ? FPM_UNIT_MATRIX : FPM_UNIT_VALU;
     if (stats)

@@ -52,6 +52,11 @@ __host__ __device__ inline uint32_t slot_dwords(uint32_t len)
 // fingerprints, the occurrence half in the low word and the counters'
 // thermometer expansion in the high word; a pair survives when both words'
 // XOR popcounts are <= 2k.
+// Pop32P / Pop64P / Qgram32P: the Pop32 / Pop64 / Qgram32 keys and test over
+// a dictionary and a query batch whose length blocks are ordered by key
+// popcount: since F_D = popc(kq ^ kw) >= |pq - pw|, a group of pairs whose
+// popcount ranges lie more than the threshold apart cannot survive and is
+// skipped untested (kernel variants only; the keys are the base kind's).
 enum KeyKind : int {
     kPop32 = 0,
     kPop64 = 1,
@@ -62,10 +67,22 @@ enum KeyKind : int {
     kAsym32 = 6,
     kAsym64 = 7,
     kQgram32 = 8,
-    kCombo64 = 9
+    kCombo64 = 9,
+    kPop32P = 10,
+    kPop64P = 11,
+    kQgram32P = 12
 };
 
-__host__ __device__ inline bool key_is_64(int kind) { return kind == kPop64 || kind == kAsym64 || kind == kCombo64; }
+__host__ __device__ inline bool key_is_64(int kind)
+{
+    return kind == kPop64 || kind == kAsym64 || kind == kCombo64 || kind == kPop64P;
+}
+
+// The popcount-ordered kernel variant of a key kind (-1: none).
+__host__ __device__ inline int pop_pruned_kind(int kind)
+{
+    return kind == kPop32 ? kPop32P : kind == kPop64 ? kPop64P : kind == kQgram32 ? kQgram32P : -1;
+}
 
 struct StrSetView {
     const uint32_t *perm;  // sorted -> caller index
@@ -104,6 +121,7 @@ struct MatchCounters {
     uint64_t *n_out;        // matches found (may exceed capacity)
     uint64_t *survivors;    // pairs verified
     uint64_t *verify_cells; // sum (2k+1) * min(m, n)
+    uint64_t *pruned;       // examined pairs skipped by popcount order (never tested)
 };
 
 // Destination of the last pass of the match-list sort (out == nullptr: none).

@@ -132,6 +132,17 @@ template <>
 struct Filter<kQgram32> : Filter<kPop32> {
 };
 
+// The popcount-ordered variants test pairs exactly as their base kinds.
+template <>
+struct Filter<kPop32P> : Filter<kPop32> {
+};
+template <>
+struct Filter<kPop64P> : Filter<kPop64> {
+};
+template <>
+struct Filter<kQgram32P> : Filter<kPop32> {
+};
+
 // Combined fingerprints: each word's XOR popcount against 2k; the AND of the
 // two tests has its sign bit set iff both parts pass.
 template <>
@@ -212,18 +223,21 @@ __host__ __device__ constexpr uint32_t filter_neg()
 {
     return KIND == kAsym32    ? 0u - (32u + K + 1u)
            : KIND == kAsym64  ? 0u - (64u + K + 1u)
-           : KIND == kQgram32 ? 0u - (4u * K + 1u)
+           : (KIND == kQgram32 || KIND == kQgram32P) ? 0u - (4u * K + 1u)
                               : 0u - (2u * K + 1u);
 }
 
-// Families of the asymmetric bound: e(q, w) - e(w, q) = pq - pw, so a pair
-// whose key popcounts differ by more than pop_gap (in key popcount units:
-// 2k for the thermometer keys, k otherwise) cannot survive.  Their blocks
-// are ordered by popcount, so a tile spans [pop(first), pop(last)].
+// Families whose blocks are ordered by key popcount, so that a tile spans
+// [pop(first), pop(last)] and a pair whose key popcounts differ by more than
+// pop_gap cannot survive: the asymmetric bound's (e(q, w) - e(w, q) =
+// pq - pw: 2k in thermometer units, k otherwise) and the paper's rule on
+// popcount-ordered blocks (F_D = popc(kq ^ kw) >= |pq - pw|: the threshold,
+// 2k or 4k for bigrams).
 template <int KIND>
 __host__ __device__ constexpr bool pop_skip()
 {
-    return KIND == kTherm32 || KIND == kAsym32 || KIND == kAsym64;
+    return KIND == kTherm32 || KIND == kAsym32 || KIND == kAsym64 || KIND == kPop32P || KIND == kPop64P ||
+           KIND == kQgram32P;
 }
 
 template <int KIND>
@@ -253,7 +267,9 @@ __device__ __forceinline__ void filter_step(typename Filter<KIND>::Key q, typena
 template <int KIND, int K>
 __host__ __device__ constexpr uint32_t pop_gap()
 {
-    return KIND == kTherm32 ? 2u * K : (uint32_t)K;
+    return KIND == kQgram32P                                          ? 4u * K
+           : (KIND == kTherm32 || KIND == kPop32P || KIND == kPop64P) ? 2u * K
+                                                                      : (uint32_t)K;
 }
 
 __device__ __forceinline__ uint32_t key_pop(uint32_t v) { return (uint32_t)__builtin_popcount(v); }
@@ -893,6 +909,8 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
     // item (band cells: (2k + 1) min(m, L) per survivor)
     uint32_t sv_item = 0;
     uint64_t survivors = 0, cells = 0;
+    // pairs of popcount-ordered blocks skipped untested (wave-uniform)
+    uint64_t pruned = 0;
 
     // first item: the global wave index (no atomics at start-up); `wave`
     // itself stays a vector value, the item is made uniform explicitly
@@ -906,8 +924,10 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
             // the whole tile is out of popcount reach: nothing to do
             if (it.qn && it.de > it.ds &&
                 pop_apart(key_pop(qkeys[it.qs]), key_pop(qkeys[it.qs + it.qn - 1]),
-                          key_pop(lane_key(dkeys[it.ds], 0)), key_pop(lane_key(dkeys[it.de - 1], 0)), kGap))
+                          key_pop(lane_key(dkeys[it.ds], 0)), key_pop(lane_key(dkeys[it.de - 1], 0)), kGap)) {
+                pruned += (uint64_t)it.qn * (it.de - it.ds);
                 it.de = it.ds;
+            }
         }
         uint32_t qlen = 0;
         if constexpr (MX != 0) {
@@ -944,6 +964,15 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
                 }
             }
         } else {
+            // popcount-ordered blocks: lane c holds the key popcount range of
+            // the item's query chunk c (32 queries; lo | hi << 8), read per
+            // pass with one v_readlane instead of two dependent scalar loads
+            uint32_t qrange = 0;
+            if constexpr (kSkip) {
+                if (lane < (it.qn + 31u) / 32u)
+                    qrange = key_pop(((const Key *)a.q.key)[it.qs + 32u * lane]) |
+                             (key_pop(((const Key *)a.q.key)[it.qs + min(32u * lane + 31u, it.qn - 1u)]) << 8);
+            }
             // two words per lane: words e0 + lane and e0 + 64 + lane
             Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
             Key wb_next = (it.ds + 64 + lane < it.de) ? dkeys[it.ds + 64 + lane] : Key(0);
@@ -967,8 +996,11 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
                     const uint32_t nqc = min(2u * kChunk, it.qn - j0);
                     const cptr<Key> qk = qkeys + it.qs + j0;  // key arrays carry 64 padding entries
                     if constexpr (kSkip) {
-                        if (pop_apart(key_pop(qk[0]), key_pop(qk[nqc - 1]), glo, ghi, kGap))
+                        const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)qrange, (int)(j0 >> 5));
+                        if (pop_apart(r & 0xFFu, r >> 8, glo, ghi, kGap)) {
+                            pruned += nqc * min(128u, it.de - e0);
                             continue;
+                        }
                     }
                     uint32_t ma = 0, mb = 0;
                     if (nqc > (uint32_t)kChunk) {
@@ -1016,14 +1048,18 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
         red[3 * wave] = survivors;
         red[3 * wave + 1] = cells;
         red[3 * wave + 2] = ocount;
+        if constexpr (kSkip)
+            red[3 * kWaves + 1 + wave] = pruned;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t sv = 0, ce = 0, o = 0, cnt[kWaves];
+        uint64_t sv = 0, ce = 0, o = 0, pr = 0, cnt[kWaves];
         for (int w = 0; w < kWaves; ++w) {
             sv += red[3 * w];
             ce += red[3 * w + 1];
             cnt[w] = red[3 * w + 2];
+            if constexpr (kSkip)
+                pr += red[3 * kWaves + 1 + w];
         }
         for (int w = 0; w < kWaves; ++w) {
             red[3 * w + 2] = o;  // exclusive prefix: the wave's first output slot
@@ -1037,6 +1073,8 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
             atomicAdd((unsigned long long *)A->ctr.survivors, (unsigned long long)sv);
         if (ce)
             atomicAdd((unsigned long long *)A->ctr.verify_cells, (unsigned long long)ce);
+        if (pr)
+            atomicAdd((unsigned long long *)A->ctr.pruned, (unsigned long long)pr);
         red[3 * kWaves] = base;
     }
     __syncthreads();
@@ -1317,6 +1355,12 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int met
         return launch_kind<kQgram32>(a, metric, k, persistent, persistent_blocks, host_items, s);
     case kCombo64:
         return launch_kind<kCombo64>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kPop32P:
+        return launch_kind<kPop32P>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kPop64P:
+        return launch_kind<kPop64P>(a, metric, k, persistent, persistent_blocks, host_items, s);
+    case kQgram32P:
+        return launch_kind<kQgram32P>(a, metric, k, persistent, persistent_blocks, host_items, s);
     default:
         return launch_kind<kAll>(a, metric, k, persistent, persistent_blocks, host_items, s);
     }

@@ -33,6 +33,8 @@ FPM_BOUND_FD, FPM_BOUND_ASYM = 0, 1
 BOUNDS = {"fd": FPM_BOUND_FD, "asym": FPM_BOUND_ASYM}
 FPM_UNIT_AUTO, FPM_UNIT_VALU, FPM_UNIT_MATRIX = 0, 1, 2
 UNITS = {"auto": FPM_UNIT_AUTO, "valu": FPM_UNIT_VALU, "matrix": FPM_UNIT_MATRIX}
+FPM_PRUNE_OFF, FPM_PRUNE_ON = 0, 1
+PRUNES = {"off": FPM_PRUNE_OFF, "on": FPM_PRUNE_ON}
 
 # every symbol include/fpm.h declares
 EXPORTS = [
@@ -61,7 +63,8 @@ class Hit(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("pairs_logical", ctypes.c_uint64), ("pairs_examined", ctypes.c_uint64),
                 ("survivors", ctypes.c_uint64), ("matches", ctypes.c_uint64), ("verify_cells", ctypes.c_uint64),
-                ("ms", ctypes.c_float), ("work_items", ctypes.c_uint32), ("filter_unit", ctypes.c_uint32)]
+                ("pairs_filtered", ctypes.c_uint64), ("ms", ctypes.c_float), ("work_items", ctypes.c_uint32),
+                ("filter_unit", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,7 +75,7 @@ class Options(ctypes.Structure):
                 ("bucket_order", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("match_capacity", ctypes.c_uint32), ("time_kernel", ctypes.c_uint32),
                 ("tail_split", ctypes.c_uint32), ("bound", ctypes.c_uint32), ("filter_unit", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("pop_prune", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -114,6 +117,8 @@ def options(**kw) -> Options:
             v = _code(BOUNDS, v)
         if k == "filter_unit":
             v = _code(UNITS, v)
+        if k == "pop_prune":
+            v = _code(PRUNES, v)
         setattr(o, k, v)
     return o
 

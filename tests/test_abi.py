@@ -75,8 +75,9 @@ def test_bench_roofline_prices_the_methods_work():
     whichever unit ran the filter test: filter ops per examined pair (occ 3,
     count16 3, count32 5, pos 9) x examined pairs + (2k+1) min(m, n) band
     cells of the survivors, over the kernel's duration, against the published
-    int-VALU peak.  Issued-VALU utilisation and the matrix-core int8 fraction
-    are reported beside it under their own names."""
+    int-VALU peak (with popcount pruning, the pricing over the pairs the
+    filter tested beside it).  Issued-VALU utilisation and the matrix-core
+    int8 fraction are reported beside it under their own names."""
     import sys as _sys
 
     _sys.path.insert(0, ROOT)
@@ -112,3 +113,54 @@ def test_bench_roofline_prices_the_methods_work():
     # no kernel time: nothing achieved, nothing divided by zero
     r = bench.roofline_of(st, None, "occ", 16, None)
     assert r["achieved"] is None and r["frac"] is None and "matrix_cores" not in r
+    # popcount pruning: the method's work stays priced per examined pair; the
+    # pricing over the pairs the filter tested is reported beside it
+    st = {"pairs_examined": 1_000_000, "pairs_filtered": 800_000, "verify_cells": 500_000,
+          "filter_unit": f.FPM_UNIT_VALU}
+    r = bench.roofline_of(st, 0.001, "occ", 32, None)
+    assert r["ops_per_launch"] == 3 * 1_000_000 + 500_000 and r["pairs_tested"] == 800_000
+    assert abs(r["frac_tested"] - 2.9e6 / 1e-6 / bench.PEAK_INT_OPS) < 1e-12
+    st["pairs_filtered"] = 1_000_000
+    assert "frac_tested" not in bench.roofline_of(st, 0.001, "occ", 32, None)
+
+
+STRUCTS = {  # header type -> binding class, header file
+    "fpm_hit": ("Hit", "fpm.h"),
+    "fpm_stats": ("Stats", "fpm.h"),
+    "fpm_options": ("Options", "fpm.h"),
+    "fpm_peaks": ("Peaks", "fpm_peak.h"),
+    "fpm_learn_config": ("LearnConfig", "fpm_learn.h"),
+    "fpm_learn_report": ("LearnReport", "fpm_learn.h"),
+}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Size and every field offset of the ctypes structures equal what a C
+    compiler lays out from include/*.h (gcc on the host)."""
+    import shutil
+    import subprocess
+
+    from paper_1711_08475_amd import fpm
+
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not found")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fpm.h"', '#include "fpm_peak.h"',
+             '#include "fpm_learn.h"', "int main(void) {"]
+    for t, (cls, _) in STRUCTS.items():
+        lines.append(f'printf("{t} size %zu\\n", sizeof({t}));')
+        for f, _ in getattr(fpm, cls)._fields_:
+            lines.append(f'printf("{t} {f} %zu\\n", offsetof({t}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    c_layout = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        t, f, v = line.split()
+        c_layout[(t, f)] = int(v)
+    for t, (cls, _) in STRUCTS.items():
+        k = getattr(fpm, cls)
+        assert ctypes.sizeof(k) == c_layout[(t, "size")], t
+        for f, _ in k._fields_:
+            assert getattr(k, f).offset == c_layout[(t, f)], (t, f)

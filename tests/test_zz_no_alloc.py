@@ -122,10 +122,10 @@ def test_noalloc_limits_and_errors(fpm):
         with pytest.raises(fpm.FpmError) as e:
             fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), n, b, out.data_ptr(), 8)
         assert e.value.status == fpm.FPM_EINVAL
-    with pytest.raises(fpm.FpmError) as e:
-        fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), nq, nb, out.data_ptr(), 8,
-                              opts=fpm.options(bound="asym"))
-    assert e.value.status == fpm.FPM_EUNSUPPORTED
+    for o in (fpm.options(bound="asym"), fpm.options(pop_prune="on")):
+        with pytest.raises(fpm.FpmError) as e:
+            fpm.fpm_match_noalloc(ix, qb.data_ptr(), qo.data_ptr(), nq, nb, out.data_ptr(), 8, opts=o)
+        assert e.value.status == fpm.FPM_EUNSUPPORTED
     # the list does not fit: the count is reported, then a call with room works
     ref = fpm.fpm_match(ix, q, "lev", 1)
     assert ref.shape[0] > 8

@@ -183,7 +183,7 @@ def serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry):
     tiles with 1, 2 or 3 batches in flight and the slab or twice the slab,
     and keep the fastest (one batch in flight unless more are at least 1%
     faster: the match kernel then runs alone and its timed duration is its
-    own).  Returns (entry, batches in flight)."""
+    own).  Returns (entry, batches in flight, ms per step)."""
     best = None
     for inflight in (1, 2, 3):
         for slab in sorted({entry["slab"], min(2 * entry["slab"], 1 << 22)}):
@@ -194,7 +194,7 @@ def serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k, entry):
             if best is None or ms < best[0] * (0.99 if inflight > best[2] else 1.0):
                 best = (ms, e, inflight)
     log(f"serving refinement: {best[2]} in flight, slab {best[1]['slab']}, {best[0]:.3f} ms/step")
-    return best[1], best[2]
+    return best[1], best[2], best[0]
 
 
 def tuned_options(fpm, torch, key, ix, qb, qo, nq, qbytes, retune: bool, metric: str, k: int, bound: str = "fd",
@@ -210,16 +210,27 @@ def tuned_options(fpm, torch, key, ix, qb, qo, nq, qbytes, retune: bool, metric:
         entry = dict(table[key])
         inflight = entry.pop("inflight", 2)
         return fpm.options(**entry), inflight, False
-    t = time.perf_counter()
-    best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2,
-                                  base=fpm.options(bound=bound, filter_unit=unit))
-    log(f"autotune {len(rows)} configs in {time.perf_counter() - t:.1f} s; fastest (qt, slab, order, tail, ms): "
-        f"{sorted(rows, key=lambda r: r[4])[:4]}")
-    entry = {k: v for k, v in best.as_dict().items()
-             if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split", "bound")}
-    entry, inflight = serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k,
-                                         dict(entry, filter_unit=fpm.UNITS[unit]))
+    # popcount pruning is tried where it applies (the paper's rule on the
+    # vector ALUs); the faster of the two refined configurations is kept
+    prunes = (0, 1) if bound == "fd" and unit != "matrix" and key.split("|")[1][:-2] in (
+        "occ", "occh", "count", "qgram") else (0,)
+    chosen = None
+    for prune in prunes:
+        t = time.perf_counter()
+        best, rows = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, metric, k, 2,
+                                      base=fpm.options(bound=bound, filter_unit=unit, pop_prune=prune))
+        log(f"autotune (pop_prune {prune}) {len(rows)} configs in {time.perf_counter() - t:.1f} s; fastest "
+            f"(qt, slab, order, tail, ms): {sorted(rows, key=lambda r: r[4])[:4]}")
+        entry = {k: v for k, v in best.as_dict().items()
+                 if k in ("schedule", "queries_per_item", "slab", "bucket_order", "tail_split", "bound", "pop_prune")}
+        entry, inflight, ms = serving_refinement(fpm, torch, ix, qb, qo, nq, qbytes, metric, k,
+                                                 dict(entry, filter_unit=fpm.UNITS[unit]))
+        if chosen is None or ms < chosen[2]:
+            chosen = (entry, inflight, ms)
+    entry, inflight, _ = chosen
     entry.pop("filter_unit", None)
+    if not entry.get("pop_prune"):
+        entry.pop("pop_prune", None)
     table[key] = dict(entry, inflight=inflight)
     with open(TUNING_FILE, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)

@@ -134,7 +134,8 @@ typedef enum { FPM_UNIT_AUTO = 0, FPM_UNIT_VALU = 1, FPM_UNIT_MATRIX = 2 } fpm_f
  * popcounts differ by more than t (Eq. 1: 2k, bigrams 4k) fails the filter.
  * With pruning, a plan orders every length block of its dictionary copy
  * and of each query batch by key popcount; a group of pairs (a work item,
- * or 32 queries x 128 words) whose popcount ranges lie more than t apart is
+ * or a pass: 32 queries x 128 words on the vector ALUs, 64 queries x 32
+ * words on the matrix cores) whose popcount ranges lie more than t apart is
  * skipped untested.  Survivors, matches and pairs_examined are unchanged;
  * fpm_stats.pairs_filtered counts the pairs the filter actually tested.
  * The ordering also gathers the survivors into the work items near equal
@@ -142,9 +143,9 @@ typedef enum { FPM_UNIT_AUTO = 0, FPM_UNIT_VALU = 1, FPM_UNIT_MATRIX = 2 } fpm_f
  * mixed-length strings) and wants smaller work items than the unordered
  * layout; the tuning table records where it is on.
  *   FPM_PRUNE_OFF (default): every examined pair is tested.
- *   FPM_PRUNE_ON: the batched schedule on the vector ALUs with occurrence,
- *     occurrence-halved, count or bigram keys under FPM_BOUND_FD;
- *     FPM_EUNSUPPORTED otherwise.  The plan then holds a popcount-ordered
+ *   FPM_PRUNE_ON: the batched schedule (either filter unit) with
+ *     occurrence, occurrence-halved, count or bigram keys under
+ *     FPM_BOUND_FD; FPM_EUNSUPPORTED otherwise.  The plan then holds a popcount-ordered
  *     copy of the dictionary's strings, keys and permutation (about the
  *     index's own size). */
 typedef enum { FPM_PRUNE_OFF = 0, FPM_PRUNE_ON = 1 } fpm_pop_prune;

@@ -775,14 +775,13 @@ static fpm_status plan_create(const fpm_index *ix, uint32_t max_queries, uint64_
     // budget), the vector-ALU kernels 8
     if (p->mx_width && !(opt && opt->waves_per_cu))
         p->opt.waves_per_cu = 28;
-    // popcount pruning (on request): the batched schedule on the vector
-    // ALUs, for keys whose F_D is the popcount of their XOR
-    const bool prune_ok = !p->asym && !p->mx_width && p->opt.schedule == FPM_SCHED_BATCHED &&
-                          pop_pruned_kind(p->kind) >= 0;
+    // popcount pruning (on request): the batched schedule, for keys whose
+    // F_D is the popcount of their XOR
+    const bool prune_ok = !p->asym && p->opt.schedule == FPM_SCHED_BATCHED && pop_pruned_kind(p->kind) >= 0;
     if (p->opt.pop_prune == FPM_PRUNE_ON && !prune_ok) {
         delete p;
-        return fail(FPM_EUNSUPPORTED, "popcount pruning takes the batched schedule on the vector ALUs with "
-                                      "occurrence, occurrence-halved, count or bigram fingerprints and the paper's rule");
+        return fail(FPM_EUNSUPPORTED, "popcount pruning takes the batched schedule with occurrence, "
+                                      "occurrence-halved, count or bigram fingerprints and the paper's rule");
     }
     p->prune = p->opt.pop_prune == FPM_PRUNE_ON;
     p->pop = p->asym || p->prune;
@@ -854,7 +853,9 @@ static fpm_status enqueue_prep(fpm_plan *p, const uint8_t *d_qbytes, const uint6
     prep_strings(p->q, d_qbytes, d_qoffsets, nq, p->max_bytes, ix->d_map, ix->variant, ix->bits,
                  fps ? p->kind : kPop32, fps, p->pop, &p->ctr->err, p->scratch, s);
     if (p->mx_width)
-        launch_expand_keys((const uint32_t *)p->q.key, nq, p->mx_width, p->qexp, s);
+        // the rows follow the order the kernel reads the queries in (the
+        // popcount order when the blocks are ordered)
+        launch_expand_keys((const uint32_t *)p->q.view().key, nq, p->mx_width, p->qexp, s);
     if (plain) {
         uint32_t h_qoff[257];
         HIPCHK(hipMemcpyAsync(h_qoff, p->q.off, sizeof(h_qoff), hipMemcpyDeviceToHost, s));

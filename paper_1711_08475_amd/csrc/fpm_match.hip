@@ -930,13 +930,22 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
             }
         }
         uint32_t qlen = 0;
+        // popcount-ordered blocks: lane c holds the key popcount range of the
+        // item's query chunk c (32 queries; lo | hi << 8), read per pass with
+        // one v_readlane instead of two dependent scalar loads
+        uint32_t qrange = 0;
+        if constexpr (kSkip) {
+            if (lane < (it.qn + 31u) / 32u)
+                qrange = key_pop(((const Key *)a.q.key)[it.qs + 32u * lane]) |
+                         (key_pop(((const Key *)a.q.key)[it.qs + min(32u * lane + 31u, it.qn - 1u)]) << 8);
+        }
         if constexpr (MX != 0) {
             // matrix cores, query-stationary: the two tiles of a group of 64
             // queries stay in registers while the slab's words stream
             // through, 32 per pass (lane: word e0 + lane % 32, queries
             // 32 (lane / 32) + b of the group)
             using Op = typename MxOp<MX>::T;
-            constexpr int kT = KIND == kQgram32 ? 4 * K : 2 * K;  // F_D threshold
+            constexpr int kT = (KIND == kQgram32 || KIND == kQgram32P) ? 4 * K : 2 * K;  // F_D threshold
             constexpr int kC1 = MX - 1 - 2 * kT, kC0 = 2 * MX - 1 - 4 * kT;
             const uint32_t h = lane >> 5, col = lane & 31u;
             const uint32_t qrow = 32u * ((col >> 2) & 1u) + 4u * (col >> 3) + (col & 3u);
@@ -948,8 +957,28 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
                 const uint32_t nqc = min(64u, it.qn - j0);
                 const uint32_t nv = nqc > 32u * h ? min(32u, nqc - 32u * h) : 0u;
                 const uint32_t qm = nv >= 32u ? ~0u : (1u << nv) - 1u;
+                uint32_t plo = 0, phi = 0;  // the group's query popcount range
+                if constexpr (kSkip) {
+                    plo = (uint32_t)__builtin_amdgcn_readlane((int)qrange, (int)(j0 >> 5)) & 0xFFu;
+                    phi = (uint32_t)__builtin_amdgcn_readlane((int)qrange, (int)((j0 + nqc - 1u) >> 5)) >> 8;
+                }
                 uint32_t w_next = (it.ds + col < it.de) ? dkeys[it.ds + col] : 0u;
                 for (uint32_t e0 = it.ds; e0 < it.de; e0 += 32) {
+                    if constexpr (kSkip) {
+                        // the slab's words ascend in popcount: a group above
+                        // the queries' reach ends the slab for this group
+                        const uint32_t last = min(e0 + 31u, it.de - 1u) - e0;
+                        const uint32_t glo = key_pop(lane_key(w_next, 0)), ghi = key_pop(lane_key(w_next, last));
+                        if (glo > phi + kGap) {
+                            pruned += (uint64_t)nqc * (it.de - e0);
+                            break;
+                        }
+                        if (plo > ghi + kGap) {
+                            pruned += nqc * (last + 1u);
+                            w_next = (e0 + 32 + col < it.de) ? dkeys[e0 + 32 + col] : 0u;
+                            continue;
+                        }
+                    }
                     const Op wb = word_column<MX>(w_next, h);
                     w_next = (e0 + 32 + col < it.de) ? dkeys[e0 + 32 + col] : 0u;
                     uint32_t m = 0;
@@ -964,15 +993,6 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
                 }
             }
         } else {
-            // popcount-ordered blocks: lane c holds the key popcount range of
-            // the item's query chunk c (32 queries; lo | hi << 8), read per
-            // pass with one v_readlane instead of two dependent scalar loads
-            uint32_t qrange = 0;
-            if constexpr (kSkip) {
-                if (lane < (it.qn + 31u) / 32u)
-                    qrange = key_pop(((const Key *)a.q.key)[it.qs + 32u * lane]) |
-                             (key_pop(((const Key *)a.q.key)[it.qs + min(32u * lane + 31u, it.qn - 1u)]) << 8);
-            }
             // two words per lane: words e0 + lane and e0 + 64 + lane
             Key wa_next = (it.ds + lane < it.de) ? dkeys[it.ds + lane] : Key(0);
             Key wb_next = (it.ds + 64 + lane < it.de) ? dkeys[it.ds + 64 + lane] : Key(0);
@@ -998,6 +1018,13 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
                     if constexpr (kSkip) {
                         const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)qrange, (int)(j0 >> 5));
                         if (pop_apart(r & 0xFFu, r >> 8, glo, ghi, kGap)) {
+                            // the item's queries ascend in popcount: a chunk
+                            // above the words' reach ends the item's chunks
+                            // for this word group
+                            if ((r & 0xFFu) > ghi + kGap) {
+                                pruned += (it.qn - j0) * min(128u, it.de - e0);
+                                break;
+                            }
                             pruned += nqc * min(128u, it.de - e0);
                             continue;
                         }
@@ -1319,14 +1346,25 @@ hipError_t launch_match(const MatchArgs &a, int key_kind, int key_width, int met
                         uint32_t persistent_blocks, uint32_t host_items, hipStream_t s)
 {
     if (key_width) {
-        if ((key_width != 16 && key_width != 32) || (key_kind != kPop32 && key_kind != kQgram32))
+        if (key_width != 16 && key_width != 32)
             return hipErrorInvalidValue;
-        if (key_width == 16)
-            return key_kind == kPop32
-                       ? launch_kind<kPop32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
-                       : launch_kind<kQgram32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s);
-        return key_kind == kPop32 ? launch_kind<kPop32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s)
-                                  : launch_kind<kQgram32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        const bool w16 = key_width == 16;
+        switch (key_kind) {
+        case kPop32:
+            return w16 ? launch_kind<kPop32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                       : launch_kind<kPop32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        case kQgram32:
+            return w16 ? launch_kind<kQgram32, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                       : launch_kind<kQgram32, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        case kPop32P:
+            return w16 ? launch_kind<kPop32P, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                       : launch_kind<kPop32P, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        case kQgram32P:
+            return w16 ? launch_kind<kQgram32P, 16>(a, metric, k, persistent, persistent_blocks, host_items, s)
+                       : launch_kind<kQgram32P, 32>(a, metric, k, persistent, persistent_blocks, host_items, s);
+        default:
+            return hipErrorInvalidValue;
+        }
     }
     switch (key_kind) {
     case kPop32:

@@ -46,15 +46,23 @@ CASES = [
 ]
 
 
+MATRIX_OK = {(oracle.OCC, 16), (oracle.OCC, 32), (oracle.OCCH, 16), (oracle.COUNT, 16), (oracle.QGRAM, 16),
+             (oracle.QGRAM, 32)}
+
+
 @pytest.mark.parametrize("variant,bits,metric,k", CASES)
 @pytest.mark.parametrize("which", ["english", "mixed"])
-def test_pruned_match_equals_oracle(fpm, variant, bits, metric, k, which):
+@pytest.mark.parametrize("unit", ["valu", "matrix"])
+def test_pruned_match_equals_oracle(fpm, variant, bits, metric, k, which, unit):
+    if unit == "matrix" and (variant, bits) not in MATRIX_OK:
+        pytest.skip("the matrix cores take 16- and 32-bit keys whose F_D is the popcount of their XOR")
     d, q = datagen.workload("english_10k_q1k") if which == "english" else \
         datagen.mixed_workload(3000, 3000, 400, 17)
-    say("prune", which, NAMES[variant], bits, metric, k)
+    say("prune", unit, which, NAMES[variant], bits, metric, k)
     ix = fpm.fpm_build_fingerprints(d, variant, bits, "common")
     got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=64, slab=512,
-                                                          pop_prune="on"), with_stats=True)
+                                                          pop_prune="on", filter_unit=unit), with_stats=True)
+    assert st["filter_unit"] == fpm.UNITS[unit]
     assert np.array_equal(got, ref_match(which, d, q, metric, k))
     ex, surv, _ = oracle.filter_stats(d, q, variant, bits, fpm.fpm_get_map(ix), metric, k)
     assert (st["pairs_examined"], st["survivors"]) == (ex, surv)
@@ -85,8 +93,10 @@ def spread_workload(seed):
     return datagen.to_csr(words), datagen.to_csr(queries), mp
 
 
-@pytest.mark.parametrize("variant,bits", [(oracle.OCC, 16), (oracle.OCC, 32), (oracle.COUNT, 32)])
-def test_pruning_skips_tiles_and_passes(fpm, variant, bits):
+@pytest.mark.parametrize("variant,bits,unit", [(oracle.OCC, 16, "valu"), (oracle.OCC, 32, "valu"),
+                                               (oracle.COUNT, 32, "valu"), (oracle.OCC, 16, "matrix"),
+                                               (oracle.OCC, 32, "matrix")])
+def test_pruning_skips_tiles_and_passes(fpm, variant, bits, unit):
     """Popcounts spread over 1..16 in each length block: with tiles from
     16 x 64 to 1024 x 1M, whole items and 32 x 128 passes are skipped (with
     the narrow tiles, fewer pairs are filtered than examined) and nothing
@@ -100,10 +110,10 @@ def test_pruning_skips_tiles_and_passes(fpm, variant, bits):
         ref = oracle.match(d, q, metric, k)
         ex, surv, _ = oracle.filter_stats(d, q, variant, bits, mp, metric, k)
         for qt, slab, tail in [(16, 64, 0), (32, 128, 50), (64, 4096, 0), (1024, 1 << 20, 0), (48, 192, 25)]:
-            say("prune spread", NAMES[variant], bits, metric, k, qt, slab, tail)
+            say("prune spread", unit, NAMES[variant], bits, metric, k, qt, slab, tail)
             got, st = fpm.fpm_match(ix, q, metric, k, fpm.options(schedule=1, queries_per_item=qt, slab=slab,
-                                                                  tail_split=tail, pop_prune="on"),
-                                    with_stats=True)
+                                                                  tail_split=tail, pop_prune="on",
+                                                                  filter_unit=unit), with_stats=True)
             assert np.array_equal(got, ref)
             assert (st["pairs_examined"], st["survivors"]) == (ex, surv)
             assert st["pairs_filtered"] <= st["pairs_examined"]
@@ -131,7 +141,8 @@ def test_pruning_when_everything_survives(fpm):
             assert st["survivors"] == st["pairs_examined"] == st["pairs_filtered"]
 
 
-def test_pruned_plan_replays_and_two_in_flight(fpm):
+@pytest.mark.parametrize("unit", ["valu", "matrix"])
+def test_pruned_plan_replays_and_two_in_flight(fpm, unit):
     """Device-scheduled plans with pruning, replayed through their graphs and
     run two at a time on their own streams, with a smaller second batch: every
     run returns the oracle's list."""
@@ -144,10 +155,10 @@ def test_pruned_plan_replays_and_two_in_flight(fpm):
     qb = torch.from_numpy(q[0].copy()).cuda()
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
     torch.cuda.synchronize()
-    opts = fpm.options(schedule=1, queries_per_item=128, slab=1024, pop_prune="on")
+    opts = fpm.options(schedule=1, queries_per_item=128, slab=1024, pop_prune="on", filter_unit=unit)
     plans = [fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, opts) for _ in range(2)]
     for r in range(3):
-        say("prune replay", r)
+        say("prune replay", unit, r)
         for p in plans:
             fpm.fpm_plan_run(p, qb.data_ptr(), qo.data_ptr(), nq)
         for p in plans:
@@ -166,7 +177,7 @@ def test_pruning_errors(fpm):
     ix_pos = fpm.fpm_build_fingerprints(d, "pos", 16, "common")
     for o, index in [(fpm.options(schedule=1, pop_prune="on"), ix_pos),
                      (fpm.options(schedule=0, pop_prune="on"), ix),
-                     (fpm.options(schedule=1, pop_prune="on", filter_unit="matrix"), ix),
+                     (fpm.options(schedule=2, pop_prune="on"), ix),
                      (fpm.options(schedule=1, pop_prune="on", bound="asym"), ix)]:
         with pytest.raises(fpm.FpmError) as e:
             fpm.fpm_match(index, q, "ham", 1, o)

@@ -366,7 +366,8 @@ fpm_status fpm_match_noalloc(const fpm_index *ix, const uint8_t *d_qbytes, const
 /* Autotuner for the batched schedule: times every combination of
  * queries_per_item in {16, 32, 64, 128, 256}, slab in {512, 1024, 2048,
  * 4096, 8192, 16384} and both bucket orders on the given device queries with
- * the tail split and filter rule (bound) of *best (on entry), then the
+ * the tail split, filter rule (bound), filter unit and popcount pruning of
+ * *best (on entry), then the
  * fastest of those with tail splits 10, 25 and 40 (100 = none), then times the
  * four fastest configurations again with max(8, 4 * repeats) runs each and
  * writes the fastest of those into *best (its schedule = FPM_SCHED_BATCHED).

@@ -49,6 +49,8 @@ def parse(argv=None):
     ap.add_argument("--seed", type=int, default=41)
     ap.add_argument("--filter-unit", default="auto", choices=["auto", "valu", "matrix"],
                     help="where the filter test runs (fpm_options.filter_unit)")
+    ap.add_argument("--pop-prune", default="off", choices=["off", "on"],
+                    help="popcount pruning of the filtered form (fpm_options.pop_prune)")
     return ap.parse_args(argv)
 
 
@@ -77,7 +79,7 @@ def run(args, on_row=None):
                 ref = fpm.fpm_plan_copy_matches(plan)
                 del plan
             best, _ = fpm.fpm_autotune(ix, qb.data_ptr(), qo.data_ptr(), nq, qbytes, "ham", 1, 2,
-                                       base=fpm.options(filter_unit=args.filter_unit))
+                                       base=fpm.options(filter_unit=args.filter_unit, pop_prune=args.pop_prune))
             plan = fpm.fpm_plan_create(ix, nq, qbytes, "ham", 1, best)
             ms, st = time_plan(fpm, torch, plan, qb, qo, nq, args.steps, args.warmup)
             got = fpm.fpm_plan_copy_matches(plan)
@@ -98,6 +100,7 @@ def run(args, on_row=None):
                 "matches": int(got.shape[0]),
                 "examined": st["pairs_examined"],
                 "survivors": st["survivors"],
+                "tested": st["pairs_filtered"],
                 "tiles": [best.queries_per_item, best.slab, best.bucket_order, best.tail_split],
             }
             out.append((row, got, fpm.fpm_get_map(ix)))

@@ -636,9 +636,11 @@ __device__ __forceinline__ void drain(const MatchArgs &a, const Item &it, const 
     const bool ok = act && d <= (uint32_t)K;
     const uint64_t mm = __ballot(ok);
     if (mm) {
-        if (ok)
-            out[ocount + lanes_below(mm)] = ((uint64_t)it.qperm[tq] << (a.wbits + 2)) |
-                                            ((uint64_t)it.dperm[te] << 2) | d;
+        if (ok) {
+            // both caller indices in one memory round trip
+            const uint32_t qi = it.qperm[tq], wi = it.dperm[te];
+            out[ocount + lanes_below(mm)] = ((uint64_t)qi << (a.wbits + 2)) | ((uint64_t)wi << 2) | d;
+        }
         ocount += (uint32_t)__popcll(mm);
         if (ocount > (uint32_t)kOutFlush)
             flush(a, out, ocount, lane);

@@ -307,13 +307,20 @@ def test_match_order_across_key_widths(fpm, small, nq):
         assert np.array_equal(got, oracle.match(d, qs, oracle.LEV, 2))
 
 
-def test_deterministic_repeats(fpm, small):
+@pytest.mark.parametrize("sched,unit", [(0, "valu"), (1, "valu"), (1, "matrix")])
+def test_deterministic_repeats(fpm, small, sched, unit):
+    """Ten reruns of one configuration return the same sorted list, equal to
+    the oracle's (the queue, staging and match counter take their entries in
+    whatever order the waves reach their atomics; the sort makes the result
+    unique)."""
     d, q = small
     ix = fpm.fpm_build_fingerprints(d, "occ", 16, "common")
-    say("repeats")
-    first = fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1))
-    for _ in range(3):
-        assert np.array_equal(fpm.fpm_match(ix, q, "lev", 1, fpm.options(schedule=1)), first)
+    say("repeats", sched, unit)
+    opts = fpm.options(schedule=sched, filter_unit=unit)
+    first = fpm.fpm_match(ix, q, "lev", 1, opts)
+    assert np.array_equal(first, oracle.match(d, q, oracle.LEV, 1))
+    for _ in range(9):
+        assert np.array_equal(fpm.fpm_match(ix, q, "lev", 1, opts), first)
 
 
 # ------------------------------------------------------- URL-like and mixed

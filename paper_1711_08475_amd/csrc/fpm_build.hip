@@ -32,19 +32,57 @@ __global__ void k_lengths(const uint64_t *offsets, uint32_t n, uint32_t *len_out
     len_out[i] = L;
 }
 
+// Byte histogram of every string's bytes (the CSR range offsets[0] ..
+// offsets[n]).  The aligned middle of the range is read 16 bytes per thread
+// and load; each block counts into eight LDS copies of the histogram (copy =
+// thread index mod 8), so lanes that meet the same frequent symbol mostly
+// hit different copies instead of serialising on one address; the copies
+// are summed into the 64-bit device histogram once per block.
+constexpr uint32_t kHistCopies = 8;
+
+__device__ __forceinline__ void hist_dword(uint32_t *h, uint32_t w)
+{
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+        atomicAdd(&h[(w >> (8 * j)) & 0xFFu], 1u);
+}
+
 __global__ void __launch_bounds__(256) k_byte_hist(const uint8_t *bytes, const uint64_t *offsets, uint32_t n,
                                                    unsigned long long *hist)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[kHistCopies][257];  // padded: copies of one bin in different banks
+    for (uint32_t i = threadIdx.x; i < kHistCopies * 257; i += blockDim.x)
+        (&h[0][0])[i] = 0;
     __syncthreads();
+    uint32_t *mine = h[threadIdx.x % kHistCopies];
     const uint64_t lo = offsets[0], hi = offsets[n];
-    for (uint64_t i = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < hi;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[bytes[i]], 1u);
+    // [lo, a0): bytes before the first 16-byte aligned address; [a0, a1):
+    // whole 16-byte groups; [a1, hi): the rest (each part of [lo, hi))
+    const uint64_t skew = (16u - (((uintptr_t)bytes + lo) & 15u)) & 15u;
+    const uint64_t a0 = lo + min(skew, hi - lo);
+    const uint64_t a1 = a0 + ((hi - a0) & ~(uint64_t)15);
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
+    if (tid < a0 - lo)
+        atomicAdd(&mine[bytes[lo + tid]], 1u);
+    if (tid < hi - a1)
+        atomicAdd(&mine[bytes[a1 + tid]], 1u);
+    const uint4 *v = (const uint4 *)(bytes + a0);
+    const uint64_t nv = (a1 - a0) >> 4;
+    for (uint64_t g = tid; g < nv; g += nth) {
+        const uint4 x = v[g];
+        hist_dword(mine, x.x);
+        hist_dword(mine, x.y);
+        hist_dword(mine, x.z);
+        hist_dword(mine, x.w);
+    }
     __syncthreads();
-    if (h[threadIdx.x])
-        atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+    uint32_t t = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kHistCopies; ++c)
+        t += h[c][threadIdx.x];
+    if (t)
+        atomicAdd(&hist[threadIdx.x], (unsigned long long)t);
 }
 
 // Symbol selection.  Thread c ranks byte c among the symbols that occur:

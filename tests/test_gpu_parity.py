@@ -55,6 +55,32 @@ def test_symbol_map_and_fingerprints(fpm, small, variant, bits, symset):
     assert np.array_equal(fpm.fpm_fingerprints(ix, q), oracle.fingerprints(q, variant, bits, ref_map))
 
 
+@pytest.mark.parametrize("extra,lead", [(0, 0), (1, 0), (7, 3), (15, 0), (16, 13), (17, 1), (33, 16)])
+def test_symbol_selection_counts_every_byte(fpm, extra, lead):
+    """Symbol counts 1..48 differ by one between neighbours, so one byte
+    missed or counted twice -- in the unaligned head or tail of the byte range
+    or in its 16-byte groups -- changes the rare, common or mixed map.  The
+    total length runs through several residues mod 16, and `lead` bytes
+    before offsets[0] (outside every string) must not be counted."""
+    rng = np.random.default_rng(300 + extra)
+    counts = np.arange(1, 49)
+    pool = np.repeat(np.arange(65, 65 + 48, dtype=np.uint8), counts)
+    pool = np.concatenate([pool, np.full(100 + extra, ord("z"), dtype=np.uint8)])
+    pool = rng.permutation(pool)
+    cuts = [0]
+    while cuts[-1] < pool.size:
+        cuts.append(min(pool.size, cuts[-1] + int(rng.integers(1, 21))))
+    junk = np.full(lead, 66, dtype=np.uint8)  # a counted symbol, so counting it would show
+    d = (np.concatenate([junk, pool]), np.array(cuts, dtype=np.uint64) + np.uint64(lead))
+    hist = oracle.histogram(d)
+    assert hist[66] == 2 and hist[ord("z")] == 100 + extra
+    say("byte histogram", extra, lead)
+    for variant, bits in [(oracle.OCC, 32), (oracle.OCC, 16), (oracle.COUNT, 32)]:
+        for symset in (oracle.COMMON, oracle.RARE, oracle.MIXED):
+            ref = oracle.select_symbols(hist, variant, bits, symset)
+            assert np.array_equal(fpm.fpm_select_symbols(d, variant, bits, symset), ref), (variant, bits, symset)
+
+
 def test_url_alphabet_fingerprints(fpm):
     d, q = datagen.url_workload(3000, 100, 5)
     for variant, bits in [(oracle.OCC, 32), (oracle.COUNT, 32), (oracle.POS, 32), (oracle.OCC, 16)]:

@@ -439,12 +439,38 @@ def run_block(fpm, torch, args, workload, variant, bits, modes, unit="auto", ext
         if name in ("batched", "learned", "asym"):
             log(f"{mode} tiles ({src}): {opts.as_dict()}, {inflight} in flight")
         r, h = time_form(fpm, torch, name, mix, qb, qo, nq, qbytes, args, opts, inflight)
+        r["index"], r["opts"] = mix, opts
         results[mode], hits[mode] = r, h
         st = r["stats"]
         log(f"{mode}: {r['ms_per_step']:.3f} ms/step ({inflight} in flight), kernel {r['kernel_ms']:.3f} ms, "
             f"{r['pairs_per_s']:.3e} pairs/s, survivors {st['survivors']}, matches {h.shape[0]}, "
             f"filter unit {st['filter_unit']}, pairs tested {st['pairs_filtered']} of {st['pairs_examined']}")
     return results, hits, {"d": d, "q": q, "fp_build": fp_build, "learned_meta": meta}
+
+
+def host_end_to_end(fpm, ix, q, opts, metric, k, ref, calls=5):
+    """The host-buffer entry point (fpm_match) timed on the host clock, one
+    warm-up and `calls` timed calls: query upload over PCIe, a temporary
+    plan (its allocations, and a rerun when the default match buffer has to
+    grow), the device pipeline, and the match list's download as (query,
+    word, dist) rows.  Reported beside the device-resident value, never as
+    it."""
+    opts = fpm.options(**dict(opts.as_dict(), time_kernel=0))
+    fpm.fpm_match(ix, q, metric, k, opts)
+    ts = []
+    got = None
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        got = fpm.fpm_match(ix, q, metric, k, opts)
+        ts.append(time.perf_counter() - t0)
+    if not np.array_equal(got, ref):
+        raise SystemExit("host entry point returned a different match list")
+    ms = 1e3 * float(np.median(ts))
+    nq = q[1].size - 1
+    return {"ms_median": ms, "pairs_per_s": nq * ix.n_words / (ms * 1e-3), "calls": calls,
+            "query_bytes_up": int(q[1][-1]) + 8 * (nq + 1), "result_bytes_down": 12 * int(got.shape[0]),
+            "includes": "query upload, temporary plan (allocations, buffer growth), device pipeline, "
+                        "match-list download"}
 
 
 def forms_summary(results):
@@ -536,6 +562,9 @@ def main():
             "kernel_ms": r["alone"]["kernel_ms"], "ms_per_step": r["alone"]["ms_per_step"],
             "frac": roofline["ops_per_launch"] / (r["alone"]["kernel_ms"] * 1e-3) / PEAK_INT_OPS}
 
+    e2e = host_end_to_end(fpm, r["index"], q, r["opts"], args.metric, args.k, hits[head])
+    log(f"host entry point (PCIe included): {e2e['ms_median']:.2f} ms per call, {e2e['pairs_per_s']:.3e} pairs/s")
+
     cpu = None
     sampled_parity = None
     if not args.no_cpu_baseline:
@@ -612,6 +641,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp_build": ctx["fp_build"],
+        "host_end_to_end": e2e,
         "forms": forms_summary(results),
         "rejection_rate": 1.0 - st["survivors"] / max(st["pairs_examined"], 1),
         "speedup_vs_brute": (results["brute"]["ms_per_step"] / r["ms_per_step"]) if "brute" in results else None,

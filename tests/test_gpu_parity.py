@@ -405,8 +405,8 @@ FULL_CASES = [
     # the 1M URL-like x 10K configuration: occurrence and count at 32 bits, Lev k = 1, 2
     ("url_1m_q10k", oracle.OCC, 32, oracle.LEV, 1), ("url_1m_q10k", oracle.OCC, 32, oracle.LEV, 2),
     ("url_1m_q10k", oracle.COUNT, 32, oracle.LEV, 1), ("url_1m_q10k", oracle.COUNT, 32, oracle.LEV, 2),
-    # the batched uneven workload
-    ("mixed_2m_q64k", oracle.OCC, 32, oracle.LEV, 1),
+    # the batched uneven workload, Lev k = 1 and k = 2
+    ("mixed_2m_q64k", oracle.OCC, 32, oracle.LEV, 1), ("mixed_2m_q64k", oracle.OCC, 32, oracle.LEV, 2),
 ]
 
 
@@ -446,13 +446,14 @@ def test_full_size_sampled_parity(fpm, name, variant, bits, metric, k):
     assert fpm.fpm_filter_pairs(ix, qs, metric, k).shape[0] == surv
 
 
-def test_headline_as_benched(fpm):
-    """The benchmark's headline exactly as it is timed: 2M mixed words x
-    65,536 queries, the stored learned occ32 map, the tuning table's tiles
-    and batches in flight, one plan per batch, runs alternating over the
-    plans with the kernel-timed (split graph) and whole-graph forms: every
-    run returns the GPU brute force's list, and 48 sampled query rows equal
-    the oracle's."""
+@pytest.mark.parametrize("k", [1, 2])
+def test_headline_as_benched(fpm, k):
+    """The benchmark's headline exactly as it is timed (k = 1; k = 2 with
+    its own stored map and tuning entry): 2M mixed words x 65,536 queries,
+    the stored learned occ32 map, the tuning table's tiles and batches in
+    flight, one plan per batch, runs alternating over the plans with the
+    kernel-timed (split graph) and whole-graph forms: every run returns the
+    GPU brute force's list, and 48 sampled query rows equal the oracle's."""
     import json
     import os
 
@@ -462,22 +463,22 @@ def test_headline_as_benched(fpm):
 
     name = "mixed_2m_q64k"
     table = json.load(open(os.path.join(os.path.dirname(learn.__file__), "tuned.json")))
-    entry = dict(table[f"{name}|occ32|lev1|learned"])
+    entry = dict(table[f"{name}|occ32|lev{k}|learned"])
     inflight = entry.pop("inflight", 2)
-    mp, _ = learn.load_map(f"{name}_occ32_k1")
+    mp, _ = learn.load_map(f"{name}_occ32_k{k}")
     d, q = full_workload(name)
     nq = q[1].size - 1
-    say("headline as benched", entry, inflight)
+    say("headline as benched", k, entry, inflight)
     ix = fpm.fpm_build_fingerprints(d, "occ", 32, custom_map=mp)
     qb = torch.from_numpy(q[0].copy()).cuda()
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()
     torch.cuda.synchronize()
-    plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, fpm.options(schedule=fpm.FPM_SCHED_BRUTE))
+    plan = fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", k, fpm.options(schedule=fpm.FPM_SCHED_BRUTE))
     fpm.fpm_plan_run(plan, qb.data_ptr(), qo.data_ptr(), nq)
     brute = fpm.fpm_plan_copy_matches(plan)
     del plan
     for timed in (1, 0):
-        plans = [fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", 1, fpm.options(**entry, time_kernel=timed))
+        plans = [fpm.fpm_plan_create(ix, nq, int(q[1][-1]), "lev", k, fpm.options(**entry, time_kernel=timed))
                  for _ in range(inflight)]
         for step in range(2 * inflight):
             fpm.fpm_plan_run(plans[step % inflight], qb.data_ptr(), qo.data_ptr(), nq)
@@ -488,7 +489,7 @@ def test_headline_as_benched(fpm):
         del plans
     sample = np.random.default_rng(12).choice(nq, 48, replace=False)
     sample.sort()
-    ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, 1, length_pruned=True)
+    ref = oracle.match(d, datagen.take_csr(q, sample), oracle.LEV, k, length_pruned=True)
     ref[:, 0] = sample[ref[:, 0]]
     assert np.array_equal(brute[np.isin(brute[:, 0], sample)], ref)
 

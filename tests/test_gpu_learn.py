@@ -86,17 +86,21 @@ def test_learned_grouping_is_sound_and_beats_the_paper_map(fpm):
     assert ev["learned_survivors"] == surv_l and ev["paper_survivors"] == surv_p
 
 
-@pytest.mark.parametrize("name,bits", [("english_1m_q10k", 16), ("mixed_2m_q64k", 32)])
-def test_stored_map_claims_hold(fpm, name, bits):
-    """The committed grouping of a benchmark workload, checked against the
-    oracle on a sample of the workload's own (held-out) queries: the map is
-    valid, the oracle's F_D counts show it rejects more length-compatible
-    pairs than the paper's common map, the GPU filter keeps exactly the
-    oracle's survivors under it, and the sampled match list equals the
-    oracle's."""
+@pytest.mark.parametrize("name,bits,k", [("english_1m_q10k", 16, 1), ("english_1m_q10k", 32, 1),
+                                         ("url_1m_q10k", 32, 1), ("url_1m_q10k", 32, 2),
+                                         ("mixed_2m_q64k", 32, 1), ("mixed_2m_q64k", 32, 2)])
+def test_stored_map_claims_hold(fpm, name, bits, k):
+    """The committed grouping of a benchmark workload (every stored map:
+    English-like 16 and 32 bits, URL-like and mixed at Lev k = 1 and 2),
+    checked against the oracle on a sample of the workload's own (held-out)
+    queries: the map is valid, the oracle's F_D counts show it rejects more
+    length-compatible pairs than the paper's common map (when the learned map
+    was kept; on a tie the stored map is the paper's), the GPU filter keeps
+    exactly the oracle's survivors under it, and the sampled match list
+    equals the oracle's."""
     from paper_1711_08475_amd import learn
 
-    mp, meta = learn.load_map(f"{name}_occ{bits}_k1")
+    mp, meta = learn.load_map(f"{name}_occ{bits}_k{k}")
     if mp is None:
         pytest.skip("no stored grouping")
     assert oracle.check_map(mp, oracle.OCC, bits)
@@ -104,15 +108,15 @@ def test_stored_map_claims_hold(fpm, name, bits):
     nq = q[1].size - 1
     sample = np.arange(0, nq, nq // 400)[:400]
     qs = datagen.take_csr(q, sample)
-    say("stored map", name, bits)
+    say("stored map", name, bits, k)
     paper = oracle.select_symbols(oracle.histogram(d), oracle.OCC, bits, oracle.COMMON)
-    ex_p, surv_p, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, paper, oracle.LEV, 1)
-    ex_l, surv_l, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, mp, oracle.LEV, 1)
+    ex_p, surv_p, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, paper, oracle.LEV, k)
+    ex_l, surv_l, _ = oracle.filter_stats(d, qs, oracle.OCC, bits, mp, oracle.LEV, k)
     assert ex_p == ex_l
     say("sample rejection paper", 1 - surv_p / ex_p, "learned", 1 - surv_l / ex_l)
     if meta["chosen"] == "learned":
         assert surv_l < surv_p
     ix = fpm.fpm_build_fingerprints(d, "occ", bits, custom_map=mp)
-    assert fpm.fpm_filter_pairs(ix, qs, "lev", 1).shape[0] == surv_l
+    assert fpm.fpm_filter_pairs(ix, qs, "lev", k).shape[0] == surv_l
     qm = datagen.take_csr(qs, np.arange(0, 400, 7))
-    assert np.array_equal(fpm.fpm_match(ix, qm, "lev", 1), oracle.match(d, qm, oracle.LEV, 1, length_pruned=True))
+    assert np.array_equal(fpm.fpm_match(ix, qm, "lev", k), oracle.match(d, qm, oracle.LEV, k, length_pruned=True))

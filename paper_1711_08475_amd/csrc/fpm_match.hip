@@ -816,15 +816,23 @@ __device__ __forceinline__ void mx_tile(typename MxOp<W>::T qa, typename MxOp<W>
 // Issue priority follows the item's position in the work list, so items
 // finish roughly in the order they were taken: the hardware otherwise
 // favours the oldest waves, and an item held by a young wave can run for
-// most of the launch and set its tail.
-__device__ __forceinline__ void set_priority(uint32_t item, uint32_t n_items)
+// most of the launch and set its tail.  Over popcount-ordered blocks with
+// popcount pruning the survivors gather in the items where the two sides'
+// popcounts meet, most of all where the strings are short (keys with few
+// set bits: up to about 190 K survivors in one 256 x 1024 item of the 2M
+// mixed workload), and the end of a launch waits for those items'
+// verification; there (kOrdered), items whose shorter length is at most 7
+// take the highest level whatever their position and the others the three
+// below it by quartile.
+template <bool kOrdered>
+__device__ __forceinline__ void set_priority(uint32_t item, uint32_t n_items, uint32_t shorter)
 {
-    const uint32_t lvl = (uint32_t)(((uint64_t)item * 4u) / n_items);
-    if (lvl == 0)
+    const uint32_t lvl = (uint32_t)(((uint64_t)item * 4u) / n_items);  // quartile of the list
+    if (kOrdered ? shorter <= 7u : lvl == 0)
         __builtin_amdgcn_s_setprio(3);
-    else if (lvl == 1)
+    else if (kOrdered ? lvl == 0 : lvl == 1)
         __builtin_amdgcn_s_setprio(2);
-    else if (lvl == 2)
+    else if (kOrdered ? lvl == 1 : lvl == 2)
         __builtin_amdgcn_s_setprio(1);
     else
         __builtin_amdgcn_s_setprio(0);
@@ -920,8 +928,8 @@ __global__ void __launch_bounds__(256, MX ? 7 : 8) k_match(MatchArgs args)
     uint32_t stripe = blockIdx.x % kStripes, tries = 0;
     uint32_t item = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
     while (item < n_items) {
-        set_priority(item, n_items);
         Item it = decode_item(a, item, n_pairs);
+        set_priority<KIND == kPop32P || KIND == kPop64P || KIND == kQgram32P>(item, n_items, min(it.m, it.L));
         if constexpr (kSkip) {
             // the whole tile is out of popcount reach: nothing to do
             if (it.qn && it.de > it.ds &&

@@ -446,10 +446,11 @@ def test_full_size_sampled_parity(fpm, name, variant, bits, metric, k):
     assert fpm.fpm_filter_pairs(ix, qs, metric, k).shape[0] == surv
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_headline_as_benched(fpm, k):
+@pytest.mark.parametrize("k,unit", [(1, "valu"), (2, "valu"), (1, "matrix")])
+def test_headline_as_benched(fpm, k, unit):
     """The benchmark's headline exactly as it is timed (k = 1; k = 2 with
-    its own stored map and tuning entry): 2M mixed words x 65,536 queries,
+    its own stored map and tuning entry; the matrix-core form with its own
+    tuning entry): 2M mixed words x 65,536 queries,
     the stored learned occ32 map, the tuning table's tiles and batches in
     flight, one plan per batch, runs alternating over the plans with the
     kernel-timed (split graph) and whole-graph forms: every run returns the
@@ -463,12 +464,13 @@ def test_headline_as_benched(fpm, k):
 
     name = "mixed_2m_q64k"
     table = json.load(open(os.path.join(os.path.dirname(learn.__file__), "tuned.json")))
-    entry = dict(table[f"{name}|occ32|lev{k}|learned"])
+    entry = dict(table[f"{name}|occ32|lev{k}|learned" + ("|matrix" if unit == "matrix" else "")])
+    entry["filter_unit"] = fpm.FPM_UNIT_MATRIX if unit == "matrix" else fpm.FPM_UNIT_VALU
     inflight = entry.pop("inflight", 2)
     mp, _ = learn.load_map(f"{name}_occ32_k{k}")
     d, q = full_workload(name)
     nq = q[1].size - 1
-    say("headline as benched", k, entry, inflight)
+    say("headline as benched", k, unit, entry, inflight)
     ix = fpm.fpm_build_fingerprints(d, "occ", 32, custom_map=mp)
     qb = torch.from_numpy(q[0].copy()).cuda()
     qo = torch.from_numpy(q[1].view(np.int64).copy()).cuda()

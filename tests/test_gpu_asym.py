@@ -181,6 +181,7 @@ def test_asym_edges_and_errors(fpm, small):
 
 @pytest.mark.parametrize("name,variant,bits,metric,k", [
     ("english_1m_q10k", "occ", 16, oracle.LEV, 1), ("url_1m_q10k", "occ", 32, oracle.LEV, 2),
+    ("mixed_2m_q64k", "occ", 32, oracle.LEV, 2),
 ])
 def test_asym_full_size_sampled_parity(fpm, name, variant, bits, metric, k):
     """Full size in the benchmark's launch configuration (batched, persistent,
